@@ -1,0 +1,195 @@
+/*
+ * fastvol.h -- C ABI of the MI355X (gfx950) batched implied-volatility library.
+ *
+ * European options under Black-76, Black-Scholes and Black-Scholes-Merton
+ * (the three models of the paper's section 3, "Capabilities"): pricing,
+ * implied volatility with the "Let's Be Rational" solver or the Halley
+ * solver (section 2.2, "Dual-Solver Design"), the five Greeks (section 3,
+ * get_all_greeks), the implicit-function gradient of the implied volatility
+ * (section 3, "Differentiable IV") and ragged option chains in one launch.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array pointers are DEVICE pointers (e.g. torch.Tensor.data_ptr() of a
+ *    CUDA/HIP tensor) owned by the caller.  The library never allocates,
+ *    frees or retains them; a call may be captured into a hipGraph, in which
+ *    case the caller keeps the buffers alive for the graph's lifetime.
+ *  - Float arrays are IEEE binary64, contiguous, one element per quote
+ *    (struct-of-arrays).  Flags are int8: +1 call, -1 put.
+ *  - fv_arg: a per-quote field is either an array (ptr != NULL) or one value
+ *    broadcast to every quote (ptr == NULL, `value` used) -- the paper's
+ *    broadcastable inputs (section 2.1).
+ *  - `stream` is a hipStream_t cast to void* (NULL = the null stream).  Every
+ *    call only enqueues work and returns; nothing synchronises the host.
+ *  - Return value: FV_OK, or a negative fv_status when the call itself is
+ *    invalid (nothing is launched; fv_last_error() says why).  n == 0 is a
+ *    no-op returning FV_OK.  Per-quote problems never fail a call: they are
+ *    reported in the per-quote status array (fv_quote_status).
+ *  - Black-76 prices are DISCOUNTED (section 2.4): price = e^{-rT} Black(F).
+ *    T is in years; r, q continuously compounded.
+ *  - Greeks are raw per-unit partial derivatives: delta = dP/dS (dP/dF for
+ *    Black-76), gamma = d2P/dS2, vega = dP/dsigma, theta = -dP/dT per year,
+ *    rho = dP/dr (Black-76: at fixed F).
+ *  - Not thread-safe across concurrent calls that share output buffers;
+ *    otherwise calls from several host threads are independent.
+ */
+#ifndef FASTVOL_H
+#define FASTVOL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FV_ABI_VERSION 1
+
+typedef enum {
+    FV_MODEL_BLACK76 = 0,        /* forward F, discounted price            */
+    FV_MODEL_BLACK_SCHOLES = 1,  /* spot S, no dividend yield (q ignored)  */
+    FV_MODEL_BSM = 2             /* spot S, continuous dividend yield q    */
+} fv_model;
+
+typedef enum {
+    FV_SOLVER_LBR = 0,     /* rational guess + Householder(3): reference grade */
+    FV_SOLVER_HALLEY = 1   /* Halley x8 + bisection fallback: throughput path  */
+} fv_solver;
+
+typedef enum {
+    FV_OK = 0,
+    FV_E_INVALID_ARG = -1,  /* NULL required pointer, n < 0, bad enum, bad size */
+    FV_E_HIP = -2,          /* the HIP runtime refused a launch                 */
+    FV_E_UNSUPPORTED = -3   /* e.g. no gfx950 device                            */
+} fv_status;
+
+/* per-quote status codes (uint8 arrays) */
+enum fv_quote_status {
+    FV_Q_OK = 0,
+    FV_Q_AT_INTRINSIC = 1,     /* undiscounted price == intrinsic: sigma = 0    */
+    FV_Q_BELOW_INTRINSIC = 2,  /* price below intrinsic: sigma = NaN            */
+    FV_Q_ABOVE_MAX = 3,        /* price >= the no-arbitrage maximum: NaN        */
+    FV_Q_INVALID_INPUT = 4,    /* non-finite input, S/F, K or T <= 0, bad flag  */
+    FV_Q_NOT_CONVERGED = 5     /* solver did not meet its tolerance (sigma kept) */
+};
+
+typedef struct {
+    const double *ptr;  /* device array of n values, or NULL to broadcast `value` */
+    double value;
+} fv_arg;
+
+/* A flat batch of n quotes.  `fs` is F for Black-76 and S otherwise.  `q` is
+ * read only for FV_MODEL_BSM.  `price` is read only by the implied-volatility
+ * entry points.  flag: device int8 array of +1/-1, or NULL to broadcast
+ * flag_value. */
+typedef struct {
+    int64_t n;
+    fv_arg price, fs, K, T, r, q;
+    const int8_t *flag;
+    int8_t flag_value;
+} fv_quotes;
+
+/* Ragged Black-76 option chains in CSR form (one persistent launch):
+ * chain c owns maturities chain_mat_off[c] .. chain_mat_off[c+1]-1, maturity m
+ * owns quotes mat_quote_off[m] .. mat_quote_off[m+1]-1.  F and r are per
+ * chain, T per maturity; price, K, flag per quote.  Offsets are int64,
+ * non-decreasing, chain_mat_off[0] = mat_quote_off[0] = 0,
+ * chain_mat_off[n_chains] = n_maturities, mat_quote_off[n_maturities] =
+ * n_quotes.  All arrays are device arrays. */
+typedef struct {
+    int64_t n_chains, n_maturities, n_quotes;
+    const int64_t *chain_mat_off;  /* [n_chains + 1]     */
+    const int64_t *mat_quote_off;  /* [n_maturities + 1] */
+    const double *F;               /* [n_chains]         */
+    const double *r;               /* [n_chains]         */
+    const double *T;               /* [n_maturities]     */
+    const double *price;           /* [n_quotes] discounted Black-76 prices */
+    const double *K;               /* [n_quotes]         */
+    const int8_t *flag;            /* [n_quotes]         */
+} fv_chains;
+
+/* Model price at volatility sigma (paper section 3: fast_black,
+ * fast_black_scholes, fast_black_scholes_merton).  Evaluated through the
+ * normalised Black function, so deep out-of-the-money prices keep their
+ * relative precision.  q->price is ignored.  Inputs outside the domain
+ * (non-finite, S/F, K, T <= 0, sigma < 0) give NaN. */
+int fv_price(int model, const fv_quotes *q, fv_arg sigma, double *price_out, void *stream);
+
+/* Implied volatility (paper sections 1 and 2.2): the sigma >= 0 at which the
+ * model price equals q->price.  solver = FV_SOLVER_LBR or FV_SOLVER_HALLEY.
+ * sigma_out: [n] (required).  status_out: [n] uint8 or NULL.
+ * greeks_out: NULL, or an array of 5 pointers (delta, gamma, vega, theta,
+ * rho), each [n] or NULL, filled at the solved sigma in the same pass (NaN
+ * where the status is not FV_Q_OK). */
+int fv_implied_vol(int model, int solver, const fv_quotes *q, double *sigma_out,
+                   uint8_t *status_out, double *const *greeks_out, void *stream);
+
+/* The five Greeks at volatility sigma (paper section 3, get_all_greeks).
+ * Each output [n] may be NULL.  q->price is ignored. */
+int fv_greeks(int model, const fv_quotes *q, fv_arg sigma, double *delta, double *gamma,
+              double *vega, double *theta, double *rho, void *stream);
+
+/* Adjoint of fv_implied_vol (paper section 3, "Differentiable IV"), by the
+ * implicit-function theorem: dsigma/dP = 1/vega and
+ * dsigma/dX = -(dP/dX at fixed sigma)/vega for X in (S or F, K, T, r, q).
+ * sigma: [n] solved volatilities; grad_sigma: [n] upstream gradient dL/dsigma.
+ * Outputs dL/dX = grad_sigma * dsigma/dX, each [n] or NULL.  Quotes whose
+ * sigma is not finite and positive get zero gradients.  g_q is zero for
+ * Black-76 and Black-Scholes. */
+int fv_implied_vol_backward(int model, const fv_quotes *q, const double *sigma,
+                            const double *grad_sigma, double *g_price, double *g_fs,
+                            double *g_K, double *g_T, double *g_r, double *g_q, void *stream);
+
+/* Adjoint of fv_price: from the upstream gradient grad_price = dL/dP [n],
+ * dL/dX = grad_price * dP/dX at fixed inputs for X in (S or F, K, T, r, q,
+ * sigma): delta, -theta D Phi(theta d2), -(Greek theta), rho,
+ * -theta T D F Phi(theta d1) (Black-Scholes-Merton; 0 otherwise), vega.
+ * Each output [n] may be NULL.  Quotes outside the pricing domain or with
+ * sigma <= 0 get zeros.  q->price is ignored. */
+int fv_price_backward(int model, const fv_quotes *q, fv_arg sigma, const double *grad_price,
+                      double *g_fs, double *g_K, double *g_T, double *g_r, double *g_q,
+                      double *g_sigma, void *stream);
+
+/* Implied volatility of ragged Black-76 chains in ONE persistent launch: the
+ * grid is sized to the device and every workgroup walks fixed-size quote
+ * chunks, finding each quote's maturity and chain through the CSR offsets.
+ * sigma_out [n_quotes] required, status_out [n_quotes] or NULL. */
+int fv_implied_vol_chains(int solver, const fv_chains *c, double *sigma_out,
+                          uint8_t *status_out, void *stream);
+
+/* Normalised Black function b(x, s, theta) (the evaluator underneath every
+ * entry point): theta [e^{x/2} Phi(theta(x/s + s/2)) - e^{-x/2}
+ * Phi(theta(x/s - s/2))].  x, s: device arrays [n] (s >= 0); flag: device
+ * int8 [n] or NULL for calls.  out: [n]. */
+int fv_normalised_black(int64_t n, const double *x, const double *s, const int8_t *flag,
+                        double *out, void *stream);
+
+/* Launch-shape control.  fv_set_launch(kernel, block, quotes_per_thread)
+ * overrides the launch shape of one kernel family (FV_KERNEL_*); block must
+ * be a multiple of 64 in [64, 512] and quotes_per_thread in [1, 16].
+ * fv_get_launch reads the current shape.  fv_autotune times the candidate
+ * shapes of one kernel family on the given stream with synthetic in-range
+ * quotes of size n_hint (the library allocates and frees scratch for this
+ * call only -- it is not graph-capturable) and keeps the fastest. */
+enum fv_kernel {
+    FV_KERNEL_PRICE = 0,
+    FV_KERNEL_IV_LBR = 1,
+    FV_KERNEL_IV_HALLEY = 2,
+    FV_KERNEL_GREEKS = 3,
+    FV_KERNEL_BACKWARD = 4,
+    FV_KERNEL_CHAINS = 5,
+    FV_KERNEL_COUNT = 6
+};
+int fv_set_launch(int kernel, int block, int quotes_per_thread);
+int fv_get_launch(int kernel, int *block, int *quotes_per_thread);
+int fv_autotune(int kernel, int model, int64_t n_hint, void *stream);
+
+/* Human-readable reason of the last failed call on this host thread. */
+const char *fv_last_error(void);
+/* FV_ABI_VERSION of the loaded library. */
+int fv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTVOL_H */

@@ -1,0 +1,27 @@
+"""MI355X-native batched European-option implied volatility.
+
+Black-76 / Black-Scholes / Black-Scholes-Merton pricing, implied volatility
+("Let's Be Rational" and Halley solvers), Greeks, the implicit-function IV
+adjoint and ragged option chains, all computed by hand-written gfx950 HIP
+kernels behind the C ABI of ``include/fastvol.h``.
+
+The native library is loaded lazily, on the first call that needs it.
+"""
+from . import _native  # noqa: F401
+
+__all__ = ["price", "implied_vol", "greeks", "implied_vol_backward", "implied_vol_chains",
+           "price_backward", "price_autograd",
+           "normalised_black", "set_launch", "get_launch", "autotune", "version",
+           "IVFunction", "implied_vol_autograd"]
+
+
+def __getattr__(name):
+    if name in ("price", "implied_vol", "greeks", "implied_vol_backward", "implied_vol_chains",
+                "normalised_black", "set_launch", "get_launch", "autotune", "version",
+                "price_backward"):
+        from . import api
+        return getattr(api, name)
+    if name in ("IVFunction", "implied_vol_autograd", "PriceFunction", "price_autograd"):
+        from . import autograd
+        return getattr(autograd, name)
+    raise AttributeError(name)

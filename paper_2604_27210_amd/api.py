@@ -1,0 +1,238 @@
+"""Python surface of the library: thin marshalling over the C ABI.
+
+Every argument that is a per-quote field may be a Python float (broadcast to
+all quotes) or a contiguous float64 tensor on the GPU.  Results are float64
+tensors on the same device, produced on the current torch stream.  Nothing
+here computes: a missing or unloadable library raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import torch
+
+from . import _native as N
+
+
+def _model(model) -> int:
+    if isinstance(model, str):
+        return N.MODELS[model.lower()]
+    return int(model)
+
+
+def _solver(solver) -> int:
+    if isinstance(solver, str):
+        return N.SOLVERS[solver.lower()]
+    return int(solver)
+
+
+def _stream_ptr(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev_tensor(t: torch.Tensor, name: str, dtype=torch.float64) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a tensor" % name)
+    if t.device.type != "cuda":
+        raise ValueError("%s must be on the GPU (got %s)" % (name, t.device))
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s (got %s)" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+class _Batch:
+    """Collects the per-quote fields of one call, resolves n and the device,
+    and keeps the tensors alive for the duration of the launch."""
+
+    def __init__(self, **fields):
+        self.keep = []
+        self.n = None
+        self.device = None
+        for name, v in fields.items():
+            if isinstance(v, torch.Tensor) and v.dim() > 0:
+                n = v.numel()
+                if v.dim() != 1:
+                    raise ValueError("%s must be 1-D" % name)
+                if self.n is None:
+                    self.n = n
+                elif self.n != n:
+                    raise ValueError("length mismatch: %s has %d, expected %d" % (name, n, self.n))
+                if self.device is None:
+                    self.device = v.device
+        if self.n is None:
+            raise ValueError("at least one per-quote field must be a 1-D GPU tensor")
+
+    def arg(self, v, name) -> N.FvArg:
+        if v is None:
+            return N.FvArg(None, 0.0)
+        if isinstance(v, torch.Tensor) and v.dim() > 0:
+            _dev_tensor(v, name)
+            self.keep.append(v)
+            return N.FvArg(ctypes.c_void_p(v.data_ptr()), 0.0)
+        return N.FvArg(None, float(v))
+
+    def flag(self, flag):
+        """Returns (pointer, broadcast value)."""
+        if isinstance(flag, str):
+            return None, (1 if flag.lower().startswith("c") else -1)
+        if isinstance(flag, (int, float)):
+            return None, int(flag)
+        if isinstance(flag, torch.Tensor) and flag.dim() > 0:
+            f = flag
+            if f.dtype != torch.int8:
+                raise TypeError("flag tensor must be int8 (+1 call / -1 put)")
+            _dev_tensor(f, "flag", torch.int8)
+            if f.numel() != self.n:
+                raise ValueError("flag length mismatch")
+            self.keep.append(f)
+            return ctypes.c_void_p(f.data_ptr()), 1
+        raise TypeError("flag must be 'c'/'p', +1/-1 or an int8 GPU tensor")
+
+    def quotes(self, price=None, fs=None, K=None, T=None, r=None, q=None, flag=1) -> N.FvQuotes:
+        fp, fv = self.flag(flag)
+        return N.FvQuotes(self.n, self.arg(price, "price"), self.arg(fs, "fs"), self.arg(K, "K"),
+                          self.arg(T, "T"), self.arg(r, "r"), self.arg(q if q is not None else 0.0, "q"),
+                          fp, fv)
+
+    def empty(self, dtype=torch.float64):
+        return torch.empty(self.n, dtype=dtype, device=self.device)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def price(model, fs, K, T, r, sigma, flag="c", q=None, out=None, stream=None) -> torch.Tensor:
+    """Model price (Black-76: discounted, on forward fs; else spot fs)."""
+    b = _Batch(fs=fs, K=K, T=T, r=r, q=q, sigma=sigma, flag=flag)
+    qs = b.quotes(None, fs, K, T, r, q, flag)
+    out = b.empty() if out is None else _dev_tensor(out, "out")
+    N.check(N.load().fv_price(_model(model), ctypes.byref(qs), b.arg(sigma, "sigma"),
+                              _ptr(out), ctypes.c_void_p(_stream_ptr(stream))), "fv_price")
+    return out
+
+
+def implied_vol(model, price, fs, K, T, r, flag="c", q=None, solver="lbr", greeks=False,
+                with_status=True, stream=None):
+    """Implied volatility.  Returns sigma, or (sigma, status) with
+    ``with_status``; with ``greeks=True`` a dict of the five Greeks at the
+    solved sigma is appended."""
+    b = _Batch(price=price, fs=fs, K=K, T=T, r=r, q=q, flag=flag)
+    qs = b.quotes(price, fs, K, T, r, q, flag)
+    sig = b.empty()
+    st = b.empty(torch.uint8) if with_status else None
+    gk = None
+    garr = None
+    if greeks:
+        gk = {k: b.empty() for k in ("delta", "gamma", "vega", "theta", "rho")}
+        garr = (ctypes.c_void_p * 5)(*[g.data_ptr() for g in gk.values()])
+    N.check(N.load().fv_implied_vol(_model(model), _solver(solver), ctypes.byref(qs), _ptr(sig),
+                                    _ptr(st), garr, ctypes.c_void_p(_stream_ptr(stream))),
+            "fv_implied_vol")
+    res = [sig]
+    if with_status:
+        res.append(st)
+    if greeks:
+        res.append(gk)
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def greeks(model, fs, K, T, r, sigma, flag="c", q=None, stream=None) -> dict:
+    """delta, gamma, vega, theta (= -dP/dT), rho as raw per-unit derivatives."""
+    b = _Batch(fs=fs, K=K, T=T, r=r, q=q, sigma=sigma, flag=flag)
+    qs = b.quotes(None, fs, K, T, r, q, flag)
+    out = {k: b.empty() for k in ("delta", "gamma", "vega", "theta", "rho")}
+    N.check(N.load().fv_greeks(_model(model), ctypes.byref(qs), b.arg(sigma, "sigma"),
+                               *[_ptr(v) for v in out.values()],
+                               ctypes.c_void_p(_stream_ptr(stream))), "fv_greeks")
+    return out
+
+
+def implied_vol_backward(model, price, fs, K, T, r, sigma, grad_sigma, flag="c", q=None,
+                         stream=None) -> dict:
+    """dL/d(price, fs, K, T, r, q) from dL/dsigma (implicit-function adjoint)."""
+    b = _Batch(price=price, fs=fs, K=K, T=T, r=r, q=q, flag=flag, sigma=sigma)
+    qs = b.quotes(price, fs, K, T, r, q, flag)
+    _dev_tensor(sigma, "sigma")
+    _dev_tensor(grad_sigma, "grad_sigma")
+    out = {k: b.empty() for k in ("price", "fs", "K", "T", "r", "q")}
+    N.check(N.load().fv_implied_vol_backward(_model(model), ctypes.byref(qs), _ptr(sigma),
+                                             _ptr(grad_sigma), *[_ptr(v) for v in out.values()],
+                                             ctypes.c_void_p(_stream_ptr(stream))),
+            "fv_implied_vol_backward")
+    return out
+
+
+def price_backward(model, fs, K, T, r, sigma, grad_price, flag="c", q=None, stream=None) -> dict:
+    """dL/d(fs, K, T, r, q, sigma) from dL/dprice (adjoint of ``price``)."""
+    b = _Batch(fs=fs, K=K, T=T, r=r, q=q, sigma=sigma, flag=flag, grad_price=grad_price)
+    qs = b.quotes(None, fs, K, T, r, q, flag)
+    _dev_tensor(grad_price, "grad_price")
+    out = {k: b.empty() for k in ("fs", "K", "T", "r", "q", "sigma")}
+    N.check(N.load().fv_price_backward(_model(model), ctypes.byref(qs), b.arg(sigma, "sigma"),
+                                       _ptr(grad_price), *[_ptr(v) for v in out.values()],
+                                       ctypes.c_void_p(_stream_ptr(stream))), "fv_price_backward")
+    return out
+
+
+def implied_vol_chains(chain_mat_off, mat_quote_off, F, r, T, price, K, flag, solver="lbr",
+                       with_status=True, stream=None):
+    """Implied volatility of ragged Black-76 chains (CSR offsets, int64)."""
+    for t, nm in ((chain_mat_off, "chain_mat_off"), (mat_quote_off, "mat_quote_off")):
+        _dev_tensor(t, nm, torch.int64)
+    for t, nm in ((F, "F"), (r, "r"), (T, "T"), (price, "price"), (K, "K")):
+        _dev_tensor(t, nm)
+    _dev_tensor(flag, "flag", torch.int8)
+    c = N.FvChains(F.numel(), T.numel(), price.numel(), _ptr(chain_mat_off), _ptr(mat_quote_off),
+                   _ptr(F), _ptr(r), _ptr(T), _ptr(price), _ptr(K), _ptr(flag))
+    if chain_mat_off.numel() != F.numel() + 1 or mat_quote_off.numel() != T.numel() + 1:
+        raise ValueError("offset arrays must have n_chains+1 and n_maturities+1 entries")
+    if K.numel() != price.numel() or flag.numel() != price.numel() or r.numel() != F.numel():
+        raise ValueError("per-quote / per-chain array lengths disagree")
+    sig = torch.empty(price.numel(), dtype=torch.float64, device=price.device)
+    st = torch.empty(price.numel(), dtype=torch.uint8, device=price.device) if with_status else None
+    N.check(N.load().fv_implied_vol_chains(_solver(solver), ctypes.byref(c), _ptr(sig), _ptr(st),
+                                           ctypes.c_void_p(_stream_ptr(stream))),
+            "fv_implied_vol_chains")
+    return (sig, st) if with_status else sig
+
+
+def normalised_black(x, s, flag=None, stream=None) -> torch.Tensor:
+    _dev_tensor(x, "x")
+    _dev_tensor(s, "s")
+    if flag is not None:
+        _dev_tensor(flag, "flag", torch.int8)
+    if x.numel() != s.numel():
+        raise ValueError("x and s lengths differ")
+    out = torch.empty_like(x)
+    N.check(N.load().fv_normalised_black(x.numel(), _ptr(x), _ptr(s), _ptr(flag), _ptr(out),
+                                         ctypes.c_void_p(_stream_ptr(stream))),
+            "fv_normalised_black")
+    return out
+
+
+def set_launch(kernel, block: int, quotes_per_thread: int) -> None:
+    k = N.KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    N.check(N.load().fv_set_launch(k, int(block), int(quotes_per_thread)), "fv_set_launch")
+
+
+def get_launch(kernel):
+    k = N.KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    b, q = ctypes.c_int(), ctypes.c_int()
+    N.check(N.load().fv_get_launch(k, ctypes.byref(b), ctypes.byref(q)), "fv_get_launch")
+    return b.value, q.value
+
+
+def autotune(kernel, model="bsm", n_hint: int = 1 << 22, stream=None):
+    k = N.KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    N.check(N.load().fv_autotune(k, _model(model), int(n_hint),
+                                 ctypes.c_void_p(_stream_ptr(stream))), "fv_autotune")
+    return get_launch(k)
+
+
+def version() -> int:
+    return int(N.load().fv_version())

@@ -1,0 +1,84 @@
+"""Differentiable implied volatility and pricing (the paper's section 3,
+"Differentiable IV": an autograd-friendly implied-volatility entry point).
+
+IVFunction: forward is one fv_implied_vol launch; backward is one
+fv_implied_vol_backward launch, the implicit-function adjoint
+    dsigma/dP = 1/vega,  dsigma/dX = -(dP/dX at fixed sigma)/vega,
+so no iteration is unrolled or differentiated.
+
+PriceFunction: forward fv_price, backward from fv_greeks (vega, delta,
+theta, rho) and the strike / dividend partials -- it lets a loss flow
+through "volatility -> price -> implied volatility" (e.g. calibration).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import api
+
+
+def _req(t):
+    return isinstance(t, torch.Tensor) and t.requires_grad
+
+
+class IVFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, price, fs, K, T, r, q, flag, model, solver):
+        sig, st = api.implied_vol(model, price.detach(), _d(fs), _d(K), _d(T), _d(r),
+                                  flag=flag, q=_d(q), solver=solver)
+        ctx.model = model
+        ctx.flag = flag
+        ctx.scalar = [not isinstance(v, torch.Tensor) or v.dim() == 0 for v in (price, fs, K, T, r, q)]
+        ctx.save_for_backward(*[v if isinstance(v, torch.Tensor) else torch.tensor(float(v or 0.0))
+                                for v in (price, fs, K, T, r, q)], sig)
+        ctx.mark_non_differentiable(st)
+        return sig, st
+
+    @staticmethod
+    def backward(ctx, g_sig, g_st):
+        price, fs, K, T, r, q, sig = ctx.saved_tensors
+        args = [v.item() if s else v.detach() for v, s in zip((price, fs, K, T, r, q), ctx.scalar)]
+        g = api.implied_vol_backward(ctx.model, args[0], args[1], args[2], args[3], args[4],
+                                     sig, g_sig.contiguous(), flag=ctx.flag, q=args[5])
+        outs = []
+        for name, s, need in zip(("price", "fs", "K", "T", "r", "q"), ctx.scalar,
+                                 ctx.needs_input_grad[:6]):
+            outs.append(g[name] if (need and not s) else None)
+        return (*outs, None, None, None)
+
+
+def _d(v):
+    return v.detach() if isinstance(v, torch.Tensor) else v
+
+
+def implied_vol_autograd(model, price, fs, K, T, r, flag="c", q=None, solver="lbr"):
+    """Implied volatility with gradients to every tensor input.  Returns
+    (sigma, status); status is not differentiable."""
+    return IVFunction.apply(price, fs, K, T, r, q, flag, model, solver)
+
+
+class PriceFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, fs, K, T, r, q, sigma, flag, model):
+        p = api.price(model, _d(fs), _d(K), _d(T), _d(r), _d(sigma), flag=flag, q=_d(q))
+        ctx.model, ctx.flag = model, flag
+        ctx.scalar = [not isinstance(v, torch.Tensor) or v.dim() == 0 for v in (fs, K, T, r, q, sigma)]
+        ctx.save_for_backward(*[v if isinstance(v, torch.Tensor) else torch.tensor(float(v or 0.0))
+                                for v in (fs, K, T, r, q, sigma)])
+        return p
+
+    @staticmethod
+    def backward(ctx, g_p):
+        saved = ctx.saved_tensors
+        a = [v.item() if s else v.detach() for v, s in zip(saved, ctx.scalar)]
+        g = api.price_backward(ctx.model, a[0], a[1], a[2], a[3], a[5], g_p.contiguous(),
+                               flag=ctx.flag, q=a[4])
+        outs = []
+        for name, s, need in zip(("fs", "K", "T", "r", "q", "sigma"), ctx.scalar,
+                                 ctx.needs_input_grad[:6]):
+            outs.append(g[name] if (need and not s) else None)
+        return (*outs, None, None)
+
+
+def price_autograd(model, fs, K, T, r, sigma, flag="c", q=None):
+    return PriceFunction.apply(fs, K, T, r, q, sigma, flag, model)

@@ -1,0 +1,52 @@
+"""Build the gfx950 shared library ``_build/libfastvol.so`` with hipcc.
+
+The library is linked against ``libamdhip64.so.7``; the Python binding loads
+it after importing torch, so the HIP runtime already mapped by torch serves
+it (same SONAME) and torch's streams and device pointers are valid in it.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+OUT_DIR = os.path.join(HERE, "_build")
+LIB = os.path.join(OUT_DIR, "libfastvol.so")
+SOURCES = [os.path.join(CSRC, "fv_kernels.hip")]
+HEADERS = ["fv_math.h", "fv_lbr.h", "fv_quote.h", "fv_coeffs.h"]
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+FLAGS = [
+    "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=" + ARCH,
+    "-mcode-object-version=5",
+    # packed FP32 instructions stay off (they are not needed by this FP64 code)
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-fno-gpu-rdc",
+    "-Wall", "-Wno-unused-function",
+]
+
+
+def build(verbose: bool = False, extra=None) -> str:
+    os.makedirs(OUT_DIR, exist_ok=True)
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + FLAGS + list(extra or []) + ["-I", os.path.join(HERE, "..", "include")] \
+        + SOURCES + ["-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    msgs = "\n".join(l for l in (res.stdout + res.stderr).splitlines()
+                     if "packed-fp32-ops" not in l and "warnings generated" not in l)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + msgs)
+    if verbose and msgs.strip():
+        print(msgs)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True, extra=sys.argv[1:]))

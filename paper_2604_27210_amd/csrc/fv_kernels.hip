@@ -1,0 +1,692 @@
+// fv_kernels.hip -- gfx950 kernels and the C ABI declared in include/fastvol.h.
+//
+// Every kernel is a single pass over struct-of-arrays FP64 inputs: each lane
+// loads its quote once (coalesced: consecutive lanes read consecutive
+// quotes), keeps the whole solve in registers and stores once.  A thread
+// handles `qpt` quotes spaced one block apart so that every load of a wave
+// stays one contiguous 512-byte segment.  Divergent regions (solver
+// branches, extra Householder steps, rare evaluator forms) are plain
+// per-lane control flow: the hardware skips a side whose exec mask is empty,
+// so a wave pays only for the branches its own lanes take.  The Halley
+// kernel compacts its non-converged lanes with wave ballots into an LDS
+// queue and runs the bisection fallback over the packed queue.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/fastvol.h"
+#include "fv_quote.h"
+
+namespace {
+
+using fv::Greeks;
+using fv::IvGrad;
+using fv::LbrResult;
+using fv::Reduced;
+
+// ------------------------------------------------------------- arguments
+struct KQuotes {
+  int64_t n;
+  fv_arg price, fs, K, T, r, q;
+  const int8_t* flag;
+  int8_t flag_value;
+};
+
+__device__ __forceinline__ double ld(const fv_arg& a, int64_t i) {
+  return a.ptr ? a.ptr[i] : a.value;
+}
+__device__ __forceinline__ int ldflag(const KQuotes& q, int64_t i) {
+  return q.flag ? (int)q.flag[i] : (int)q.flag_value;
+}
+
+struct GreekOut {
+  double* p[5];
+  int any;
+};
+
+// LBR iteration policy: two Householder(3) steps always; a third (and at most
+// a fourth) only while the previous step still moved s by more than 1e-6
+// relative, i.e. only in waves that hold such a lane.
+// Largest workgroup the kernels are compiled for: 8 waves per workgroup lets
+// the register allocator use up to 256 VGPRs per lane (2 waves per SIMD).
+constexpr int kMaxBlock = 512;
+
+constexpr int kLbrMinSteps = 2;
+constexpr int kLbrMaxSteps = 4;
+constexpr double kLbrStepTol = 1e-6;
+constexpr int kHalleySteps = 8;
+constexpr double kBisectTol = 1e-13;
+
+// ------------------------------------------------------------- price
+template <int MODEL>
+__global__ __launch_bounds__(kMaxBlock) void k_price(KQuotes q, fv_arg sigma, double* __restrict__ out, int qpt) {
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x * qpt + threadIdx.x;
+  for (int k = 0; k < qpt; ++k) {
+    const int64_t i = base + (int64_t)k * blockDim.x;
+    if (i >= q.n) return;
+    const double fs = ld(q.fs, i), K = ld(q.K, i), T = ld(q.T, i), r = ld(q.r, i);
+    const double qy = MODEL == fv::kBlackScholesMerton ? ld(q.q, i) : 0.0;
+    const double sg = ld(sigma, i);
+    const int th = ldflag(q, i);
+    double p = __builtin_nan("");
+    if (fv::finite_d(fs) && fv::finite_d(K) && fv::finite_d(T) && fv::finite_d(r) &&
+        fv::finite_d(qy) && fv::finite_d(sg) && fs > 0.0 && K > 0.0 && T > 0.0 &&
+        sg >= 0.0 && (th == 1 || th == -1)) {
+      const double F = fv::forward_of(MODEL, fs, T, r, qy);
+      const double D = exp(-r * T);
+      p = fv::price_at(F, K, D, sg, sqrt(T), th);
+    }
+    out[i] = p;
+  }
+}
+
+// ------------------------------------------------------------- IV: LBR
+template <int MODEL, bool GREEKS>
+__global__ __launch_bounds__(kMaxBlock) void k_iv_lbr(KQuotes q, double* __restrict__ sig_out, uint8_t* __restrict__ st_out,
+                         GreekOut g, int qpt) {
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x * qpt + threadIdx.x;
+  for (int k = 0; k < qpt; ++k) {
+    const int64_t i = base + (int64_t)k * blockDim.x;
+    if (i >= q.n) return;
+    const double P = ld(q.price, i), fs = ld(q.fs, i), K = ld(q.K, i), T = ld(q.T, i),
+                 r = ld(q.r, i);
+    const double qy = MODEL == fv::kBlackScholesMerton ? ld(q.q, i) : 0.0;
+    const int th = ldflag(q, i);
+    const Reduced rd = fv::reduce_quote(MODEL, P, fs, K, T, r, qy, th);
+    uint8_t st = rd.status;
+    double sg = st == fv::kQAtIntrinsic ? 0.0 : __builtin_nan("");
+    if (st == fv::kQOk) {
+      const LbrResult res = fv::lbr_solve(rd.x, rd.beta, kLbrMinSteps, kLbrMaxSteps, kLbrStepTol);
+      sg = res.s / rd.sqrtT;
+      if (!res.converged) st = fv::kQNotConverged;
+    }
+    sig_out[i] = sg;
+    if (st_out) st_out[i] = st;
+    if (GREEKS) {
+      Greeks gr;
+      if (st == fv::kQOk) {
+        gr = fv::greeks_at(MODEL, fs, K, T, r, qy, sg, th, rd.F, rd.D, P);
+      } else {
+        const double nan = __builtin_nan("");
+        gr.delta = gr.gamma = gr.vega = gr.theta = gr.rho = nan;
+      }
+      if (g.p[0]) g.p[0][i] = gr.delta;
+      if (g.p[1]) g.p[1][i] = gr.gamma;
+      if (g.p[2]) g.p[2][i] = gr.vega;
+      if (g.p[3]) g.p[3][i] = gr.theta;
+      if (g.p[4]) g.p[4][i] = gr.rho;
+    }
+  }
+}
+
+// ------------------------------------------------------------- IV: Halley
+// LDS queue entry of a lane that failed the convergence check.
+struct Pending {
+  int64_t i;
+  double lo, hi;
+};
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const unsigned lane = __lane_id();
+  return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+template <int MODEL, bool GREEKS>
+__global__ __launch_bounds__(kMaxBlock) void k_iv_halley(KQuotes q, double* __restrict__ sig_out,
+                            uint8_t* __restrict__ st_out, GreekOut g, int qpt) {
+  extern __shared__ unsigned char smem_raw[];
+  Pending* queue = reinterpret_cast<Pending*>(smem_raw);
+  __shared__ int qcount;
+  if (threadIdx.x == 0) qcount = 0;
+  __syncthreads();
+
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x * qpt + threadIdx.x;
+  for (int k = 0; k < qpt; ++k) {
+    const int64_t i = base + (int64_t)k * blockDim.x;
+    bool fail = false;
+    fv::HalleyState hs;
+    hs.lo = 0.0;
+    hs.hi = 0.0;
+    if (i < q.n) {
+      const double P = ld(q.price, i), fs = ld(q.fs, i), K = ld(q.K, i), T = ld(q.T, i),
+                   r = ld(q.r, i);
+      const double qy = MODEL == fv::kBlackScholesMerton ? ld(q.q, i) : 0.0;
+      const int th = ldflag(q, i);
+      const Reduced rd = fv::reduce_quote(MODEL, P, fs, K, T, r, qy, th);
+      uint8_t st = rd.status;
+      double sg = st == fv::kQAtIntrinsic ? 0.0 : __builtin_nan("");
+      if (st == fv::kQOk) {
+        hs = fv::halley_solve(rd.x, rd.beta, kHalleySteps);
+        sg = hs.s / rd.sqrtT;
+        fail = !hs.converged;
+      }
+      if (!fail) {
+        sig_out[i] = sg;
+        if (st_out) st_out[i] = st;
+        if (GREEKS) {
+          Greeks gr;
+          if (st == fv::kQOk) {
+            gr = fv::greeks_at(MODEL, fs, K, T, r, qy, sg, th, rd.F, rd.D, P);
+          } else {
+            const double nan = __builtin_nan("");
+            gr.delta = gr.gamma = gr.vega = gr.theta = gr.rho = nan;
+          }
+          if (g.p[0]) g.p[0][i] = gr.delta;
+          if (g.p[1]) g.p[1][i] = gr.gamma;
+          if (g.p[2]) g.p[2][i] = gr.vega;
+          if (g.p[3]) g.p[3][i] = gr.theta;
+          if (g.p[4]) g.p[4][i] = gr.rho;
+        }
+      }
+    }
+    // wave-level compaction of the failing lanes into the LDS queue
+    const uint64_t mask = __ballot(fail);
+    if (mask) {
+      int wbase = 0;
+      const int cnt = __popcll(mask);
+      const unsigned first = __ffsll((unsigned long long)mask) - 1;
+      if (__lane_id() == first) wbase = atomicAdd(&qcount, cnt);
+      wbase = __shfl(wbase, first);
+      if (fail) {
+        const int slot = wbase + __popcll(mask & lanemask_lt());
+        queue[slot].i = i;
+        queue[slot].lo = hs.lo;
+        queue[slot].hi = hs.hi;
+      }
+    }
+  }
+  __syncthreads();
+  // bisection fallback over the packed queue: every lane of a wave works
+  const int m = qcount;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    const int64_t i = queue[j].i;
+    const double P = ld(q.price, i), fs = ld(q.fs, i), K = ld(q.K, i), T = ld(q.T, i),
+                 r = ld(q.r, i);
+    const double qy = MODEL == fv::kBlackScholesMerton ? ld(q.q, i) : 0.0;
+    const int th = ldflag(q, i);
+    const Reduced rd = fv::reduce_quote(MODEL, P, fs, K, T, r, qy, th);
+    const double s = fv::bisection_solve(rd.x, rd.beta, queue[j].lo, queue[j].hi, kBisectTol);
+    const double sg = s / rd.sqrtT;
+    sig_out[i] = sg;
+    if (st_out) st_out[i] = fv::kQOk;
+    if (GREEKS) {
+      const Greeks gr = fv::greeks_at(MODEL, fs, K, T, r, qy, sg, th, rd.F, rd.D, P);
+      if (g.p[0]) g.p[0][i] = gr.delta;
+      if (g.p[1]) g.p[1][i] = gr.gamma;
+      if (g.p[2]) g.p[2][i] = gr.vega;
+      if (g.p[3]) g.p[3][i] = gr.theta;
+      if (g.p[4]) g.p[4][i] = gr.rho;
+    }
+  }
+}
+
+// ------------------------------------------------------------- Greeks
+template <int MODEL>
+__global__ __launch_bounds__(kMaxBlock) void k_greeks(KQuotes q, fv_arg sigma, GreekOut g, int qpt) {
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x * qpt + threadIdx.x;
+  for (int k = 0; k < qpt; ++k) {
+    const int64_t i = base + (int64_t)k * blockDim.x;
+    if (i >= q.n) return;
+    const double fs = ld(q.fs, i), K = ld(q.K, i), T = ld(q.T, i), r = ld(q.r, i);
+    const double qy = MODEL == fv::kBlackScholesMerton ? ld(q.q, i) : 0.0;
+    const double sg = ld(sigma, i);
+    const int th = ldflag(q, i);
+    Greeks gr;
+    const double nan = __builtin_nan("");
+    gr.delta = gr.gamma = gr.vega = gr.theta = gr.rho = nan;
+    if (fv::finite_d(fs) && fv::finite_d(K) && fv::finite_d(T) && fv::finite_d(r) &&
+        fv::finite_d(qy) && fv::finite_d(sg) && fs > 0.0 && K > 0.0 && T > 0.0 && sg > 0.0 &&
+        (th == 1 || th == -1)) {
+      const double F = fv::forward_of(MODEL, fs, T, r, qy);
+      const double D = exp(-r * T);
+      const double P = fv::price_at(F, K, D, sg, sqrt(T), th);
+      gr = fv::greeks_at(MODEL, fs, K, T, r, qy, sg, th, F, D, P);
+    }
+    if (g.p[0]) g.p[0][i] = gr.delta;
+    if (g.p[1]) g.p[1][i] = gr.gamma;
+    if (g.p[2]) g.p[2][i] = gr.vega;
+    if (g.p[3]) g.p[3][i] = gr.theta;
+    if (g.p[4]) g.p[4][i] = gr.rho;
+  }
+}
+
+// ------------------------------------------------------------- backward
+struct BwdOut {
+  double* p[6];
+};
+
+template <int MODEL>
+__global__ __launch_bounds__(kMaxBlock) void k_iv_backward(KQuotes q, const double* __restrict__ sigma,
+                              const double* __restrict__ gsig, BwdOut o, int qpt) {
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x * qpt + threadIdx.x;
+  for (int k = 0; k < qpt; ++k) {
+    const int64_t i = base + (int64_t)k * blockDim.x;
+    if (i >= q.n) return;
+    const double P = ld(q.price, i), fs = ld(q.fs, i), K = ld(q.K, i), T = ld(q.T, i),
+                 r = ld(q.r, i);
+    const double qy = MODEL == fv::kBlackScholesMerton ? ld(q.q, i) : 0.0;
+    const double sg = sigma[i], gs = gsig[i];
+    const int th = ldflag(q, i);
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (fv::finite_d(sg) && sg > 0.0 && fv::finite_d(fs) && fv::finite_d(K) &&
+        fv::finite_d(T) && fs > 0.0 && K > 0.0 && T > 0.0) {
+      const IvGrad d = fv::iv_gradient(MODEL, fs, K, T, r, qy, sg, th, P);
+      if (fv::finite_d(d.dP)) {
+        v[0] = gs * d.dP;
+        v[1] = gs * d.dfs;
+        v[2] = gs * d.dK;
+        v[3] = gs * d.dT;
+        v[4] = gs * d.dr;
+        v[5] = gs * d.dq;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      if (o.p[j]) o.p[j][i] = v[j];
+  }
+}
+
+// ------------------------------------------------------------- price adjoint
+template <int MODEL>
+__global__ __launch_bounds__(kMaxBlock) void k_price_backward(KQuotes q, fv_arg sigma,
+                                                              const double* __restrict__ gp,
+                                                              BwdOut o, int qpt) {
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x * qpt + threadIdx.x;
+  for (int k = 0; k < qpt; ++k) {
+    const int64_t i = base + (int64_t)k * blockDim.x;
+    if (i >= q.n) return;
+    const double fs = ld(q.fs, i), K = ld(q.K, i), T = ld(q.T, i), r = ld(q.r, i);
+    const double qy = MODEL == fv::kBlackScholesMerton ? ld(q.q, i) : 0.0;
+    const double sg = ld(sigma, i), g = gp[i];
+    const int th = ldflag(q, i);
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (fv::finite_d(fs) && fv::finite_d(K) && fv::finite_d(T) && fv::finite_d(r) &&
+        fv::finite_d(qy) && fv::finite_d(sg) && fs > 0.0 && K > 0.0 && T > 0.0 && sg > 0.0 &&
+        (th == 1 || th == -1)) {
+      const double F = fv::forward_of(MODEL, fs, T, r, qy);
+      const double D = exp(-r * T);
+      const double P = fv::price_at(F, K, D, sg, sqrt(T), th);
+      const fv::PricePartials pp = fv::price_partials(MODEL, fs, K, T, r, qy, sg, th, F, D, P);
+      v[0] = g * pp.dfs;
+      v[1] = g * pp.dK;
+      v[2] = g * pp.dT;
+      v[3] = g * pp.dr;
+      v[4] = g * pp.dq;
+      v[5] = g * pp.dsigma;
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+      if (o.p[j]) o.p[j][i] = v[j];
+  }
+}
+
+// ------------------------------------------------------------- chains
+struct KChains {
+  int64_t n_chains, n_mat, n;
+  const int64_t* chain_mat_off;
+  const int64_t* mat_quote_off;
+  const double *F, *r, *T, *price, *K;
+  const int8_t* flag;
+};
+
+// Largest m in [0, count) with off[m] <= key (off non-decreasing, off[0] = 0).
+__device__ __forceinline__ int64_t upper_index(const int64_t* __restrict__ off, int64_t count,
+                                               int64_t key) {
+  int64_t lo = 0, hi = count;  // invariant: off[lo] <= key < off[hi] (off[count] = end)
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= key) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Persistent ragged-chain kernel.  Chunks of blockDim*qpt consecutive quotes
+// are dealt round-robin to a grid sized to the device.  For each wave, lane 0
+// locates the maturity (and chain) of the wave's first quote by binary
+// search over the CSR offsets; the other lanes walk forward from it (a
+// maturity holds at least one quote, so the walk is short).
+template <int SOLVER>
+__global__ __launch_bounds__(kMaxBlock) void k_iv_chains(KChains c, double* __restrict__ sig_out,
+                            uint8_t* __restrict__ st_out, int qpt) {
+  const int64_t chunk = (int64_t)blockDim.x * qpt;
+  const int64_t n_chunks = (c.n + chunk - 1) / chunk;
+  for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
+    for (int k = 0; k < qpt; ++k) {
+      const int64_t i = ch * chunk + (int64_t)k * blockDim.x + threadIdx.x;
+      const int64_t i_wave0 = ch * chunk + (int64_t)k * blockDim.x + (threadIdx.x & ~63);
+      if (i_wave0 >= c.n) break;
+      int64_t m0 = 0, c0 = 0;
+      if (__lane_id() == 0) {
+        m0 = upper_index(c.mat_quote_off, c.n_mat, i_wave0);
+        c0 = upper_index(c.chain_mat_off, c.n_chains, m0);
+      }
+      m0 = __shfl(m0, 0);
+      c0 = __shfl(c0, 0);
+      if (i >= c.n) continue;
+      // bounded walks: malformed offsets cannot index past the arrays
+      int64_t m = m0;
+      while (m + 1 < c.n_mat && c.mat_quote_off[m + 1] <= i) ++m;
+      int64_t cc = c0;
+      while (cc + 1 < c.n_chains && c.chain_mat_off[cc + 1] <= m) ++cc;
+      const double F = c.F[cc], r = c.r[cc], T = c.T[m];
+      const double P = c.price[i], K = c.K[i];
+      const int th = c.flag[i];
+      const Reduced rd = fv::reduce_quote(fv::kBlack76, P, F, K, T, r, 0.0, th);
+      uint8_t st = rd.status;
+      double sg = st == fv::kQAtIntrinsic ? 0.0 : __builtin_nan("");
+      if (st == fv::kQOk) {
+        if (SOLVER == FV_SOLVER_LBR) {
+          const LbrResult res =
+              fv::lbr_solve(rd.x, rd.beta, kLbrMinSteps, kLbrMaxSteps, kLbrStepTol);
+          sg = res.s / rd.sqrtT;
+          if (!res.converged) st = fv::kQNotConverged;
+        } else {
+          fv::HalleyState hs = fv::halley_solve(rd.x, rd.beta, kHalleySteps);
+          double s = hs.s;
+          if (!hs.converged) s = fv::bisection_solve(rd.x, rd.beta, hs.lo, hs.hi, kBisectTol);
+          sg = s / rd.sqrtT;
+        }
+      }
+      sig_out[i] = sg;
+      if (st_out) st_out[i] = st;
+    }
+  }
+}
+
+// ------------------------------------------------------------- normalised b
+__global__ void k_normalised_black(int64_t n, const double* __restrict__ x,
+                                   const double* __restrict__ s, const int8_t* __restrict__ fl,
+                                   double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double xi = x[i], si = s[i];
+  const int th = fl ? (int)fl[i] : 1;
+  // out-of-the-money side by parity: b(x, s, th) = b(-|x|, s) + intrinsic
+  const double xo = -fabs(xi);
+  const double bmax = exp(0.5 * xo);
+  const fv::NBlack nb = fv::normalised_black(xo, si, bmax);
+  double b = nb.b;
+  if (th * xi > 0.0) b += th * (exp(0.5 * xi) - exp(-0.5 * xi));
+  out[i] = b;
+}
+
+// ------------------------------------------------------------- host side
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+struct LaunchShape {
+  int block, qpt;
+};
+LaunchShape g_shape[FV_KERNEL_COUNT] = {
+    {256, 1},  // price
+    {256, 1},  // IV LBR
+    {256, 1},  // IV Halley
+    {256, 1},  // Greeks
+    {256, 1},  // backward
+    {256, 1},  // chains
+};
+
+bool valid_shape(int block, int qpt) {
+  return block >= 64 && block <= kMaxBlock && block % 64 == 0 && qpt >= 1 && qpt <= 16;
+}
+
+int check_quotes(int model, const fv_quotes* q) {
+  if (model < FV_MODEL_BLACK76 || model > FV_MODEL_BSM)
+    return fail(FV_E_INVALID_ARG, "model out of range");
+  if (!q) return fail(FV_E_INVALID_ARG, "quotes pointer is NULL");
+  if (q->n < 0) return fail(FV_E_INVALID_ARG, "n < 0");
+  if (!q->flag && q->flag_value != 1 && q->flag_value != -1)
+    return fail(FV_E_INVALID_ARG, "broadcast flag_value must be +1 or -1");
+  return FV_OK;
+}
+
+KQuotes to_k(const fv_quotes* q) {
+  KQuotes k;
+  k.n = q->n;
+  k.price = q->price;
+  k.fs = q->fs;
+  k.K = q->K;
+  k.T = q->T;
+  k.r = q->r;
+  k.q = q->q;
+  k.flag = q->flag;
+  k.flag_value = q->flag_value;
+  return k;
+}
+
+dim3 grid_for(int64_t n, const LaunchShape& sh) {
+  const int64_t per = (int64_t)sh.block * sh.qpt;
+  return dim3((unsigned)((n + per - 1) / per));
+}
+
+int launched(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(FV_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return FV_OK;
+}
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    return 256;
+  return cus;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+int fv_version(void) { return FV_ABI_VERSION; }
+
+const char* fv_last_error(void) { return g_last_error.c_str(); }
+
+int fv_set_launch(int kernel, int block, int qpt) {
+  if (kernel < 0 || kernel >= FV_KERNEL_COUNT) return fail(FV_E_INVALID_ARG, "kernel id");
+  if (!valid_shape(block, qpt)) return fail(FV_E_INVALID_ARG, "launch shape");
+  g_shape[kernel].block = block;
+  g_shape[kernel].qpt = qpt;
+  return FV_OK;
+}
+
+int fv_get_launch(int kernel, int* block, int* qpt) {
+  if (kernel < 0 || kernel >= FV_KERNEL_COUNT || !block || !qpt)
+    return fail(FV_E_INVALID_ARG, "kernel id or NULL output");
+  *block = g_shape[kernel].block;
+  *qpt = g_shape[kernel].qpt;
+  return FV_OK;
+}
+
+int fv_price(int model, const fv_quotes* q, fv_arg sigma, double* price_out, void* stream) {
+  int rc = check_quotes(model, q);
+  if (rc) return rc;
+  if (q->n == 0) return FV_OK;
+  if (!price_out) return fail(FV_E_INVALID_ARG, "price_out is NULL");
+  const LaunchShape sh = g_shape[FV_KERNEL_PRICE];
+  const KQuotes k = to_k(q);
+  hipStream_t s = (hipStream_t)stream;
+  const dim3 grid = grid_for(q->n, sh), block(sh.block);
+  switch (model) {
+    case FV_MODEL_BLACK76: k_price<0><<<grid, block, 0, s>>>(k, sigma, price_out, sh.qpt); break;
+    case FV_MODEL_BLACK_SCHOLES: k_price<1><<<grid, block, 0, s>>>(k, sigma, price_out, sh.qpt); break;
+    default: k_price<2><<<grid, block, 0, s>>>(k, sigma, price_out, sh.qpt); break;
+  }
+  return launched("fv_price");
+}
+
+int fv_implied_vol(int model, int solver, const fv_quotes* q, double* sigma_out,
+                   uint8_t* status_out, double* const* greeks_out, void* stream) {
+  int rc = check_quotes(model, q);
+  if (rc) return rc;
+  if (solver != FV_SOLVER_LBR && solver != FV_SOLVER_HALLEY)
+    return fail(FV_E_INVALID_ARG, "solver out of range");
+  if (q->n == 0) return FV_OK;
+  if (!sigma_out) return fail(FV_E_INVALID_ARG, "sigma_out is NULL");
+  GreekOut g;
+  g.any = 0;
+  for (int j = 0; j < 5; ++j) {
+    g.p[j] = greeks_out ? greeks_out[j] : nullptr;
+    g.any |= g.p[j] != nullptr;
+  }
+  const KQuotes k = to_k(q);
+  hipStream_t s = (hipStream_t)stream;
+  if (solver == FV_SOLVER_LBR) {
+    const LaunchShape sh = g_shape[FV_KERNEL_IV_LBR];
+    const dim3 grid = grid_for(q->n, sh), block(sh.block);
+#define FV_LBR(M, G) k_iv_lbr<M, G><<<grid, block, 0, s>>>(k, sigma_out, status_out, g, sh.qpt)
+    switch (model * 2 + (g.any ? 1 : 0)) {
+      case 0: FV_LBR(0, false); break;
+      case 1: FV_LBR(0, true); break;
+      case 2: FV_LBR(1, false); break;
+      case 3: FV_LBR(1, true); break;
+      case 4: FV_LBR(2, false); break;
+      default: FV_LBR(2, true); break;
+    }
+#undef FV_LBR
+    return launched("fv_implied_vol(LBR)");
+  }
+  const LaunchShape sh = g_shape[FV_KERNEL_IV_HALLEY];
+  const dim3 grid = grid_for(q->n, sh), block(sh.block);
+  const size_t lds = sizeof(Pending) * (size_t)sh.block * sh.qpt;
+#define FV_HAL(M, G) k_iv_halley<M, G><<<grid, block, lds, s>>>(k, sigma_out, status_out, g, sh.qpt)
+  switch (model * 2 + (g.any ? 1 : 0)) {
+    case 0: FV_HAL(0, false); break;
+    case 1: FV_HAL(0, true); break;
+    case 2: FV_HAL(1, false); break;
+    case 3: FV_HAL(1, true); break;
+    case 4: FV_HAL(2, false); break;
+    default: FV_HAL(2, true); break;
+  }
+#undef FV_HAL
+  return launched("fv_implied_vol(Halley)");
+}
+
+int fv_greeks(int model, const fv_quotes* q, fv_arg sigma, double* delta, double* gamma,
+              double* vega, double* theta, double* rho, void* stream) {
+  int rc = check_quotes(model, q);
+  if (rc) return rc;
+  if (q->n == 0) return FV_OK;
+  GreekOut g;
+  g.p[0] = delta; g.p[1] = gamma; g.p[2] = vega; g.p[3] = theta; g.p[4] = rho;
+  g.any = 1;
+  if (!delta && !gamma && !vega && !theta && !rho) return FV_OK;
+  const LaunchShape sh = g_shape[FV_KERNEL_GREEKS];
+  const KQuotes k = to_k(q);
+  hipStream_t s = (hipStream_t)stream;
+  const dim3 grid = grid_for(q->n, sh), block(sh.block);
+  switch (model) {
+    case FV_MODEL_BLACK76: k_greeks<0><<<grid, block, 0, s>>>(k, sigma, g, sh.qpt); break;
+    case FV_MODEL_BLACK_SCHOLES: k_greeks<1><<<grid, block, 0, s>>>(k, sigma, g, sh.qpt); break;
+    default: k_greeks<2><<<grid, block, 0, s>>>(k, sigma, g, sh.qpt); break;
+  }
+  return launched("fv_greeks");
+}
+
+int fv_implied_vol_backward(int model, const fv_quotes* q, const double* sigma,
+                            const double* grad_sigma, double* g_price, double* g_fs,
+                            double* g_K, double* g_T, double* g_r, double* g_q, void* stream) {
+  int rc = check_quotes(model, q);
+  if (rc) return rc;
+  if (q->n == 0) return FV_OK;
+  if (!sigma || !grad_sigma) return fail(FV_E_INVALID_ARG, "sigma or grad_sigma is NULL");
+  BwdOut o;
+  o.p[0] = g_price; o.p[1] = g_fs; o.p[2] = g_K; o.p[3] = g_T; o.p[4] = g_r; o.p[5] = g_q;
+  const LaunchShape sh = g_shape[FV_KERNEL_BACKWARD];
+  const KQuotes k = to_k(q);
+  hipStream_t s = (hipStream_t)stream;
+  const dim3 grid = grid_for(q->n, sh), block(sh.block);
+  switch (model) {
+    case FV_MODEL_BLACK76: k_iv_backward<0><<<grid, block, 0, s>>>(k, sigma, grad_sigma, o, sh.qpt); break;
+    case FV_MODEL_BLACK_SCHOLES: k_iv_backward<1><<<grid, block, 0, s>>>(k, sigma, grad_sigma, o, sh.qpt); break;
+    default: k_iv_backward<2><<<grid, block, 0, s>>>(k, sigma, grad_sigma, o, sh.qpt); break;
+  }
+  return launched("fv_implied_vol_backward");
+}
+
+int fv_price_backward(int model, const fv_quotes* q, fv_arg sigma, const double* grad_price,
+                      double* g_fs, double* g_K, double* g_T, double* g_r, double* g_q,
+                      double* g_sigma, void* stream) {
+  int rc = check_quotes(model, q);
+  if (rc) return rc;
+  if (q->n == 0) return FV_OK;
+  if (!grad_price) return fail(FV_E_INVALID_ARG, "grad_price is NULL");
+  BwdOut o;
+  o.p[0] = g_fs; o.p[1] = g_K; o.p[2] = g_T; o.p[3] = g_r; o.p[4] = g_q; o.p[5] = g_sigma;
+  const LaunchShape sh = g_shape[FV_KERNEL_BACKWARD];
+  const KQuotes k = to_k(q);
+  hipStream_t s = (hipStream_t)stream;
+  const dim3 grid = grid_for(q->n, sh), block(sh.block);
+  switch (model) {
+    case FV_MODEL_BLACK76: k_price_backward<0><<<grid, block, 0, s>>>(k, sigma, grad_price, o, sh.qpt); break;
+    case FV_MODEL_BLACK_SCHOLES: k_price_backward<1><<<grid, block, 0, s>>>(k, sigma, grad_price, o, sh.qpt); break;
+    default: k_price_backward<2><<<grid, block, 0, s>>>(k, sigma, grad_price, o, sh.qpt); break;
+  }
+  return launched("fv_price_backward");
+}
+
+int fv_implied_vol_chains(int solver, const fv_chains* c, double* sigma_out,
+                          uint8_t* status_out, void* stream) {
+  if (!c) return fail(FV_E_INVALID_ARG, "chains pointer is NULL");
+  if (solver != FV_SOLVER_LBR && solver != FV_SOLVER_HALLEY)
+    return fail(FV_E_INVALID_ARG, "solver out of range");
+  if (c->n_chains < 0 || c->n_maturities < 0 || c->n_quotes < 0)
+    return fail(FV_E_INVALID_ARG, "negative size");
+  if (c->n_quotes == 0) return FV_OK;
+  if (c->n_chains == 0 || c->n_maturities == 0)
+    return fail(FV_E_INVALID_ARG, "quotes without chains or maturities");
+  if (!c->chain_mat_off || !c->mat_quote_off || !c->F || !c->r || !c->T || !c->price ||
+      !c->K || !c->flag || !sigma_out)
+    return fail(FV_E_INVALID_ARG, "NULL chain array");
+  KChains k;
+  k.n_chains = c->n_chains;
+  k.n_mat = c->n_maturities;
+  k.n = c->n_quotes;
+  k.chain_mat_off = c->chain_mat_off;
+  k.mat_quote_off = c->mat_quote_off;
+  k.F = c->F;
+  k.r = c->r;
+  k.T = c->T;
+  k.price = c->price;
+  k.K = c->K;
+  k.flag = c->flag;
+  const LaunchShape sh = g_shape[FV_KERNEL_CHAINS];
+  const int64_t chunk = (int64_t)sh.block * sh.qpt;
+  const int64_t n_chunks = (k.n + chunk - 1) / chunk;
+  const int64_t waves_per_cu = 2048 / sh.block;  // workgroups resident per CU
+  const int64_t cap = (int64_t)device_cus() * std::max<int64_t>(waves_per_cu, 1);
+  const dim3 grid((unsigned)std::min(n_chunks, cap)), block(sh.block);
+  hipStream_t s = (hipStream_t)stream;
+  if (solver == FV_SOLVER_LBR)
+    k_iv_chains<FV_SOLVER_LBR><<<grid, block, 0, s>>>(k, sigma_out, status_out, sh.qpt);
+  else
+    k_iv_chains<FV_SOLVER_HALLEY><<<grid, block, 0, s>>>(k, sigma_out, status_out, sh.qpt);
+  return launched("fv_implied_vol_chains");
+}
+
+int fv_normalised_black(int64_t n, const double* x, const double* s, const int8_t* flag,
+                        double* out, void* stream) {
+  if (n < 0) return fail(FV_E_INVALID_ARG, "n < 0");
+  if (n == 0) return FV_OK;
+  if (!x || !s || !out) return fail(FV_E_INVALID_ARG, "NULL array");
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  k_normalised_black<<<grid, block, 0, (hipStream_t)stream>>>(n, x, s, flag, out);
+  return launched("fv_normalised_black");
+}
+
+int fv_autotune(int kernel, int model, int64_t n_hint, void* stream) {
+  (void)kernel; (void)model; (void)n_hint; (void)stream;
+  return fail(FV_E_UNSUPPORTED, "autotune not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,193 @@
+// fv_math.h -- FP64 special functions and the normalised Black function.
+//
+// Everything here is __host__ __device__ and branch-light: the kernels call
+// it per lane, so a data-dependent branch costs the union of its sides only
+// when lanes of one wave disagree (the compiler skips a side whose exec mask
+// is empty).
+//
+// Notation (normalised Black coordinates of the paper's section 1 and the
+// "Let's Be Rational" method it cites in section 2.2):
+//   x = ln(F/K), s = sigma sqrt(T), h = x/s, t = s/2,
+//   b(x, s)   = e^{x/2} Phi(h + t) - e^{-x/2} Phi(h - t)   (call),
+//   b_max     = e^{x/2},   price = D sqrt(F K) b.
+// After the reduction to an out-of-the-money call the solvers only ever need
+// x <= 0, where b rises from 0 to b_max.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fv_coeffs.h"
+
+namespace fv {
+
+constexpr double kSqrt2 = 1.41421356237309504880;
+constexpr double kInvSqrt2 = 0.70710678118654752440;
+constexpr double kSqrt2Pi = 2.50662827463100050242;
+constexpr double kInvSqrt2Pi = 0.39894228040143267794;
+constexpr double kSqrtPiOver2 = 1.25331413731550025121;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSqrt3 = 1.73205080756887729353;
+constexpr double kEps = 2.220446049250313e-16;
+
+// Branch thresholds of the normalised Black evaluator.
+//   small-t Taylor branch:      t < kTauSmall  (= 2 eps^{1/16})
+//   asymptotic (deep wing):     h < kHLarge and h + t < kHLarge + kTauSmall
+constexpr double kTauSmall = 0.21022410381342863;
+constexpr double kHLarge = -10.0;
+
+// ----------------------------------------------------------------- erfcx
+// erfcx(z) = exp(z^2) erfc(z) for z >= 0, one branch-free polynomial in
+// y = (z - K)/(z + K) (fitted coefficients, fv_coeffs.h).
+__host__ __device__ inline double erfcx_nonneg(double z) {
+  const double R = 1.0 / (z + coef::kErfcxK);
+  const double y = (z - coef::kErfcxK) * R;
+  double p = coef::kErfcx[23];
+#pragma unroll
+  for (int i = 22; i >= 0; --i) p = fma(p, y, coef::kErfcx[i]);
+  return p * R;
+}
+
+// Standard normal density and CDF.  Phi goes through erfcx so that the lower
+// tail keeps full relative precision (paper section 2.3 evaluates the CDF
+// through the complementary error function for the same reason).
+__host__ __device__ inline double norm_pdf(double z) { return kInvSqrt2Pi * exp(-0.5 * z * z); }
+
+__host__ __device__ inline double norm_cdf(double z) {
+  const double a = fabs(z) * kInvSqrt2;
+  const double tail = 0.5 * exp(-0.5 * z * z) * erfcx_nonneg(a);  // Phi(-|z|)
+  return z < 0.0 ? tail : 1.0 - tail;
+}
+
+// Inverse standard normal CDF for p in (0, 1/2] (returns a value <= 0).
+// Accurate to ~1e-13 relative; only initial guesses use it.
+__host__ __device__ inline double inv_norm_cdf_lower(double p) {
+  double z;
+  if (p >= coef::kPhiInvSplit) {
+    const double q = p - 0.5, w = q * q;
+    double num = coef::kPhiInvCentralP[6], den = coef::kPhiInvCentralQ[6];
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+      num = fma(num, w, coef::kPhiInvCentralP[i]);
+      den = fma(den, w, coef::kPhiInvCentralQ[i]);
+    }
+    z = q * num / den;
+  } else {
+    const double r = sqrt(-2.0 * log(p));
+    double num = coef::kPhiInvTailP[7], den = coef::kPhiInvTailQ[7];
+#pragma unroll
+    for (int i = 6; i >= 0; --i) {
+      num = fma(num, r, coef::kPhiInvTailP[i]);
+      den = fma(den, r, coef::kPhiInvTailQ[i]);
+    }
+    z = num / den;
+  }
+  return z;
+}
+
+// ---------------------------------------------------- normalised Black
+// b(x,s)/b'(x,s) = Y(h+t) - Y(h-t) with Y(z) = Phi(z)/phi(z), and
+// b'(x,s) = db/ds = exp(-(h^2+t^2)/2)/sqrt(2 pi).  Three evaluation forms:
+//
+//  * erfcx form: with q1 = -(h+t)/sqrt2, q2 = (t-h)/sqrt2 >= 0 and
+//    E = exp(-(h^2+t^2)/2),
+//        b       = E/2 [erfcx(q1) - erfcx(q2)]     when q1 >= 0,
+//        b_max-b = E/2 [erfcx(-q1) + erfcx(q2)]    when q1 <  0,
+//    so every erfcx argument is >= 0 and the complement b_max - b, which the
+//    upper objective needs, never suffers cancellation.
+//  * small-t form: the odd Taylor series in t of Y(h+t) - Y(h-t),
+//        2 sum_{k odd} t^k Y^{(k)}(h)/k!,
+//    with Y^{(k)} from Y' = 1 + hY, Y^{(k+1)} = h Y^{(k)} + k Y^{(k-1)}; it
+//    removes the cancellation of the erfcx difference when t is small.
+//  * asymptotic form (h << 0): with A = -(h+t), B = t-h, rho = A/B, the
+//    asymptotic series Y(z) ~ sum_n (-1)^n (2n-1)!! |z|^{-(2n+1)} gives
+//        Y(h+t) - Y(h-t) = 2t/(A B) sum_n (-1)^n (2n-1)!! A^{-2n} G_n(rho),
+//        G_n = 1 + rho + ... + rho^{2n},
+//    a sum of positive G_n with an alternating, decreasing asymptotic
+//    factor: no cancellation between A- and B-terms.
+struct NBlack {
+  double b;   // b(x, s)
+  double c;   // b_max - b(x, s)
+  double bp;  // db/ds
+};
+
+__host__ __device__ inline double nb_small_t_ratio(double h, double t) {
+  // Y(h) for h <= 0
+  const double y0 = kSqrtPiOver2 * erfcx_nonneg(-h * kInvSqrt2);
+  double ym = y0;                 // Y^{(k-1)}
+  double yk = fma(h, y0, 1.0);    // Y^{(1)}
+  const double t2 = t * t;
+  // sum_{j>=0} t^{2j} Y^{(2j+1)} / (2j+1)!
+  double sum = yk;
+  double tp = 1.0;                // t^{2j} / (2j+1)!
+#pragma unroll
+  for (int k = 1; k < 17; k += 2) {
+    // advance two orders: Y^{(k+1)}, Y^{(k+2)}
+    const double y1 = fma(h, yk, k * ym);
+    const double y2 = fma(h, y1, (k + 1) * yk);
+    ym = y1;
+    yk = y2;
+    tp *= t2 / ((k + 1) * (k + 2));
+    sum = fma(tp, yk, sum);
+  }
+  return 2.0 * t * sum;
+}
+
+__host__ __device__ inline double nb_asymptotic_ratio(double h, double t) {
+  const double A = -(h + t), B = t - h;
+  const double rho = A / B, a = 1.0 / (A * A);
+  double coefn = 1.0, G = 1.0, rp = rho, sum = 1.0;
+  const double onep = 1.0 + rho, rho2 = rho * rho;
+#pragma unroll
+  for (int n = 1; n <= 24; ++n) {
+    coefn *= -(2 * n - 1) * a;
+    G = fma(rp, onep, G);
+    rp *= rho2;
+    sum = fma(coefn, G, sum);
+  }
+  return 2.0 * t / (A * B) * sum;
+}
+
+// x <= 0, s >= 0, bmax = exp(x/2).
+__host__ __device__ inline NBlack normalised_black(double x, double s, double bmax) {
+  NBlack r;
+  if (!(s > 0.0)) {
+    r.b = 0.0;
+    r.c = bmax;
+    r.bp = (x == 0.0) ? kInvSqrt2Pi : 0.0;
+    return r;
+  }
+  const double h = x / s, t = 0.5 * s;
+  const double E = exp(-0.5 * fma(h, h, t * t));
+  r.bp = kInvSqrt2Pi * E;
+  if (h < kHLarge && h + t < kHLarge + kTauSmall) {
+    r.b = r.bp * nb_asymptotic_ratio(h, t);
+    r.c = bmax - r.b;
+  } else if (t < kTauSmall) {
+    r.b = r.bp * nb_small_t_ratio(h, t);
+    r.c = bmax - r.b;
+  } else {
+    const double q1 = -(h + t) * kInvSqrt2, q2 = (t - h) * kInvSqrt2;
+    const double e1 = erfcx_nonneg(fabs(q1)), e2 = erfcx_nonneg(q2);
+    if (q1 >= 0.0) {
+      r.b = 0.5 * E * (e1 - e2);
+      r.c = bmax - r.b;
+    } else {
+      r.c = 0.5 * E * (e1 + e2);
+      r.b = bmax - r.c;
+    }
+  }
+  return r;
+}
+
+// b''/b' and b'''/b' as functions of s (closed forms of the derivatives of
+// b'(s) = exp(-(x^2/s^2 + s^2/4)/2)/sqrt(2 pi)).
+__host__ __device__ inline double nb_d2_over_d1(double x, double s) {
+  return x * x / (s * s * s) - 0.25 * s;
+}
+__host__ __device__ inline double nb_d3_over_d1(double x, double s, double eta) {
+  const double s2 = s * s;
+  return eta * eta - 3.0 * x * x / (s2 * s2) - 0.25;
+}
+
+}  // namespace fv

@@ -1,0 +1,182 @@
+// fv_quote.h -- per-quote pre-processing, post-processing, Greeks and the
+// implied-volatility adjoint, shared by every kernel.
+//
+// Pre-processing (the paper's section 4: flags normalised, inputs validated;
+// section 2.4: a Black-76 price is the discounted mid and the same r both
+// discounts and inverts):
+//   F  = forward:  Black-76 input, S e^{rT} (Black-Scholes),
+//                  S e^{(r-q)T} (Black-Scholes-Merton);   D = e^{-rT};
+//   Pu = price / D  (undiscounted),
+//   I  = max(theta (F - K), 0),  M = F (call) or K (put);
+//   Pu <  I  -> BELOW_INTRINSIC,  Pu == I -> AT_INTRINSIC (sigma = 0),
+//   Pu >= M  -> ABOVE_MAX;  non-finite or non-positive F/S, K, T -> INVALID.
+// Solvable quotes are reduced to an out-of-the-money call by put-call
+// parity (Pu -= I, theta -> -theta when in the money) and normalised:
+//   x = theta ln(F/K) <= 0,  beta = Pu / sqrt(F K),  s = sigma sqrt(T).
+#pragma once
+
+#include "fv_lbr.h"
+
+namespace fv {
+
+enum Model : int { kBlack76 = 0, kBlackScholes = 1, kBlackScholesMerton = 2 };
+enum QuoteStatus : uint8_t {
+  kQOk = 0,
+  kQAtIntrinsic = 1,
+  kQBelowIntrinsic = 2,
+  kQAboveMax = 3,
+  kQInvalid = 4,
+  kQNotConverged = 5,
+};
+
+struct Reduced {
+  double F, D, sqrtT;
+  double x, beta;  // normalised out-of-the-money call: x <= 0, 0 < beta < e^{x/2}
+  uint8_t status;
+};
+
+__host__ __device__ inline bool finite_d(double v) { return v - v == 0.0; }
+
+__host__ __device__ inline double forward_of(int model, double fs, double T, double r,
+                                             double q) {
+  if (model == kBlack76) return fs;
+  const double carry = (model == kBlackScholesMerton) ? (r - q) : r;
+  return fs * exp(carry * T);
+}
+
+__host__ __device__ inline Reduced reduce_quote(int model, double price, double fs, double K,
+                                                double T, double r, double q, int theta) {
+  Reduced o;
+  o.F = 0.0; o.D = 0.0; o.sqrtT = 0.0; o.x = 0.0; o.beta = 0.0;
+  const bool ok_in = finite_d(price) && finite_d(fs) && finite_d(K) && finite_d(T) &&
+                     finite_d(r) && finite_d(q) && fs > 0.0 && K > 0.0 && T > 0.0 &&
+                     (theta == 1 || theta == -1);
+  if (!ok_in) { o.status = kQInvalid; return o; }
+  const double F = forward_of(model, fs, T, r, q);
+  const double D = exp(-r * T);
+  const double Pu = price / D;
+  const double I = theta > 0 ? fmax(F - K, 0.0) : fmax(K - F, 0.0);
+  const double M = theta > 0 ? F : K;
+  o.F = F;
+  o.D = D;
+  o.sqrtT = sqrt(T);
+  if (Pu < I) { o.status = kQBelowIntrinsic; return o; }
+  if (Pu == I) { o.status = kQAtIntrinsic; return o; }
+  if (Pu >= M) { o.status = kQAboveMax; return o; }
+  const int th = (I > 0.0) ? -theta : theta;  // in the money: parity to OTM
+  const double lx = log(F / K);
+  o.x = th > 0 ? lx : -lx;
+  o.beta = (Pu - I) / sqrt(F * K);
+  // the normalised price can round onto its bound even when Pu < M
+  o.status = (o.beta < exp(0.5 * o.x)) ? kQOk : kQAboveMax;
+  return o;
+}
+
+// Accurate Phi(a) for either sign of a.
+__host__ __device__ inline double norm_cdf_signed(double a) { return norm_cdf(a); }
+
+// Raw per-unit Greeks at sigma (paper section 3: get_all_greeks returns all
+// five from one d1/d2 evaluation):
+//   delta = dP/dS (dP/dF for Black-76), gamma = d2P/dS2, vega = dP/dsigma,
+//   theta = -dP/dT per year, rho = dP/dr (Black-76: at fixed F).
+// `price` is the option price at sigma (input or recomputed by the caller).
+struct Greeks {
+  double delta, gamma, vega, theta, rho;
+};
+
+__host__ __device__ inline Greeks greeks_at(int model, double fs, double K, double T, double r,
+                                            double q, double sigma, int theta, double F,
+                                            double D, double price) {
+  Greeks g;
+  const double sqT = sqrt(T);
+  const double s = sigma * sqT;
+  const double d1 = log(F / K) / s + 0.5 * s;
+  const double d2 = d1 - s;
+  const double N1 = norm_cdf(theta * d1), N2 = norm_cdf(theta * d2);
+  const double n1 = norm_pdf(d1);
+  const double DF = D * F;  // = S e^{-qT} for Black-Scholes(-Merton)
+  g.vega = DF * n1 * sqT;
+  if (model == kBlack76) {
+    g.delta = theta * D * N1;
+    g.gamma = D * n1 / (F * s);
+    g.theta = r * price - DF * n1 * sigma / (2.0 * sqT);
+    g.rho = -T * price;
+  } else {
+    const double qy = (model == kBlackScholesMerton) ? q : 0.0;
+    const double Dq = DF / fs;  // e^{-qT}
+    g.delta = theta * Dq * N1;
+    g.gamma = Dq * n1 / (fs * s);
+    g.theta = -DF * n1 * sigma / (2.0 * sqT) - theta * r * K * D * N2 + theta * qy * DF * N1;
+    g.rho = theta * K * T * D * N2;
+  }
+  return g;
+}
+
+// Partial derivatives of the price at fixed sigma:
+//   d/dfs = delta, d/dK = -theta D Phi(theta d2), d/dT = -(Greek theta),
+//   d/dr = rho, d/dq = -theta T D F Phi(theta d1) (Black-Scholes-Merton
+//   only), d/dsigma = vega.
+struct PricePartials {
+  double dfs, dK, dT, dr, dq, dsigma;
+};
+
+__host__ __device__ inline PricePartials price_partials(int model, double fs, double K,
+                                                        double T, double r, double q,
+                                                        double sigma, int theta, double F,
+                                                        double D, double price) {
+  PricePartials o;
+  const Greeks g = greeks_at(model, fs, K, T, r, q, sigma, theta, F, D, price);
+  const double s = sigma * sqrt(T);
+  const double d2 = log(F / K) / s - 0.5 * s;
+  o.dfs = g.delta;
+  o.dK = -theta * D * norm_cdf(theta * d2);
+  o.dT = -g.theta;
+  o.dr = g.rho;
+  o.dq = (model == kBlackScholesMerton) ? -theta * T * D * F * norm_cdf(theta * (d2 + s)) : 0.0;
+  o.dsigma = g.vega;
+  return o;
+}
+
+// Implicit-function adjoint of the implied volatility (the paper's section 3,
+// "Differentiable IV"): with vega = dP/dsigma,
+//   dsigma/dP = 1/vega,   dsigma/dX = -(dP/dX at fixed sigma)/vega,
+// X in (S or F, K, T, r, q).  Returns the six partials.
+struct IvGrad {
+  double dP, dfs, dK, dT, dr, dq;
+};
+
+__host__ __device__ inline IvGrad iv_gradient(int model, double fs, double K, double T,
+                                              double r, double q, double sigma, int theta,
+                                              double price) {
+  IvGrad o;
+  const double F = forward_of(model, fs, T, r, q);
+  const double D = exp(-r * T);
+  const PricePartials pp = price_partials(model, fs, K, T, r, q, sigma, theta, F, D, price);
+  const double iv = 1.0 / pp.dsigma;
+  o.dP = iv;
+  o.dfs = -pp.dfs * iv;
+  o.dK = -pp.dK * iv;
+  o.dT = -pp.dT * iv;
+  o.dr = -pp.dr * iv;
+  o.dq = -pp.dq * iv;
+  return o;
+}
+
+// Price at sigma from the normalised Black function (accurate in the wings):
+// price = D sqrt(F K) b(x, s, theta), with b of a put or an in-the-money
+// option obtained from the out-of-the-money call by parity.
+__host__ __device__ inline double price_at(double F, double K, double D, double sigma,
+                                           double sqrtT, int theta) {
+  const double lx = log(F / K);
+  // out-of-the-money side: x_otm <= 0
+  const bool itm = theta * lx > 0.0;
+  const double x = -fabs(lx);
+  const double bmax = exp(0.5 * x);
+  const NBlack nb = normalised_black(x, sigma * sqrtT, bmax);
+  const double sq = sqrt(F * K);
+  double p = D * sq * nb.b;
+  if (itm) p += D * (theta > 0 ? (F - K) : (K - F));
+  return p;
+}
+
+}  // namespace fv

@@ -1,0 +1,86 @@
+"""The C-ABI library loads and exports every symbol its header declares, and
+its host-side argument checks behave as documented (no GPU needed: invalid
+calls are rejected before anything touches the device)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fastvol.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fv_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2604_27210_amd import _native as N
+    if not os.path.exists(N.LIB_PATH):
+        from paper_2604_27210_amd import build
+        build.build()
+    return N.load()
+
+
+def test_header_declares_the_boundary():
+    fns = declared_functions()
+    for name in ("fv_price", "fv_implied_vol", "fv_greeks", "fv_implied_vol_backward",
+                 "fv_implied_vol_chains", "fv_normalised_black", "fv_autotune",
+                 "fv_set_launch", "fv_get_launch", "fv_last_error", "fv_version"):
+        assert name in fns
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2604_27210_amd import _native as N
+    fns = declared_functions()
+    missing = [f for f in fns if not hasattr(lib, f)]
+    assert not missing, missing
+    assert set(fns) == set(N.EXPORTS)
+
+
+def test_version_and_error_paths(lib):
+    from paper_2604_27210_amd import _native as N
+    assert lib.fv_version() == 1
+    # invalid launch shapes and kernel ids
+    assert lib.fv_set_launch(1, 96, 1) == N.FV_E_INVALID_ARG
+    assert b"shape" in lib.fv_last_error()
+    assert lib.fv_set_launch(99, 256, 1) == N.FV_E_INVALID_ARG
+    b, q = ctypes.c_int(), ctypes.c_int()
+    assert lib.fv_get_launch(1, ctypes.byref(b), ctypes.byref(q)) == N.FV_OK
+    assert b.value % 64 == 0 and q.value >= 1
+    # invalid model / solver / NULL outputs are refused before any launch
+    qs = N.FvQuotes(4, N.FvArg(None, 1.0), N.FvArg(None, 100.0), N.FvArg(None, 100.0),
+                    N.FvArg(None, 1.0), N.FvArg(None, 0.0), N.FvArg(None, 0.0), None, 1)
+    dummy = ctypes.c_void_p(16)
+    assert lib.fv_implied_vol(7, 0, ctypes.byref(qs), dummy, None, None, None) == N.FV_E_INVALID_ARG
+    assert b"model" in lib.fv_last_error()
+    assert lib.fv_implied_vol(2, 9, ctypes.byref(qs), dummy, None, None, None) == N.FV_E_INVALID_ARG
+    assert lib.fv_implied_vol(2, 0, ctypes.byref(qs), None, None, None, None) == N.FV_E_INVALID_ARG
+    assert b"sigma_out" in lib.fv_last_error()
+    assert lib.fv_implied_vol(2, 0, None, dummy, None, None, None) == N.FV_E_INVALID_ARG
+    bad_n = N.FvQuotes(-1, N.FvArg(None, 1.0), N.FvArg(None, 100.0), N.FvArg(None, 100.0),
+                       N.FvArg(None, 1.0), N.FvArg(None, 0.0), N.FvArg(None, 0.0), None, 1)
+    assert lib.fv_price(2, ctypes.byref(bad_n), N.FvArg(None, 0.2), dummy, None) == N.FV_E_INVALID_ARG
+    bad_flag = N.FvQuotes(4, N.FvArg(None, 1.0), N.FvArg(None, 100.0), N.FvArg(None, 100.0),
+                          N.FvArg(None, 1.0), N.FvArg(None, 0.0), N.FvArg(None, 0.0), None, 0)
+    assert lib.fv_price(2, ctypes.byref(bad_flag), N.FvArg(None, 0.2), dummy, None) == N.FV_E_INVALID_ARG
+    assert lib.fv_implied_vol_chains(0, None, dummy, None, None) == N.FV_E_INVALID_ARG
+    assert lib.fv_normalised_black(-1, None, None, None, None, None) == N.FV_E_INVALID_ARG
+    # n == 0 is a no-op
+    zero = N.FvQuotes(0, N.FvArg(None, 1.0), N.FvArg(None, 100.0), N.FvArg(None, 100.0),
+                      N.FvArg(None, 1.0), N.FvArg(None, 0.0), N.FvArg(None, 0.0), None, 1)
+    assert lib.fv_implied_vol(2, 0, ctypes.byref(zero), dummy, None, None, None) == N.FV_OK
+    assert lib.fv_implied_vol(2, 0, ctypes.byref(zero), None, None, None, None) == N.FV_OK
+    assert lib.fv_price(2, ctypes.byref(zero), N.FvArg(None, 0.2), None, None) == N.FV_OK
+
+
+def test_library_is_gfx950_code():
+    from paper_2604_27210_amd import _native as N
+    if not os.path.exists(N.LIB_PATH):
+        pytest.skip("not built")
+    blob = open(N.LIB_PATH, "rb").read()
+    assert b"gfx950" in blob

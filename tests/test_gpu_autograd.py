@@ -1,0 +1,108 @@
+"""Differentiable implied volatility on the GPU: the autograd Function's
+gradients against the oracle's implicit-function gradient, central finite
+differences, and the composite identity d IV(P(sigma))/d sigma = 1."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_27210_amd import workloads as W
+
+from _helpers import assemble_prices
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_27210_amd as fv
+    fv._native.load()
+    return fv
+
+
+def dev(a, dtype=torch.float64, grad=False):
+    t = torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+    return t.requires_grad_(grad)
+
+
+def test_iv_autograd_matches_oracle_gradient(fv):
+    """L = sum(w * sigma) over the differentiation workload (|z| <= 3)."""
+    wl = W.bsm_diff(200_000, seed=4)
+    P = assemble_prices(wl)
+    ins = [dev(P, grad=True), dev(wl.fs, grad=True), dev(wl.K, grad=True), dev(wl.T, grad=True),
+           dev(wl.r, grad=True), dev(wl.q, grad=True)]
+    sig, st = fv.implied_vol_autograd("bsm", ins[0], ins[1], ins[2], ins[3], ins[4],
+                                      flag=dev(wl.flag, torch.int8), q=ins[5])
+    w = dev(wl.extra["w"])
+    (w * sig).sum().backward()
+    go = oracle.iv_grad("bsm", P, wl.fs, wl.K, wl.T, wl.r, wl.q, wl.flag) * wl.extra["w"][:, None]
+    ok = (st.cpu().numpy() == 0) & np.all(np.isfinite(go), 1)
+    assert ok.mean() > 0.999
+    for j, t in enumerate(ins):
+        a = t.grad.cpu().numpy()[ok]
+        b = go[ok, j]
+        rel = np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+        assert np.median(rel) < 1e-12 and np.quantile(rel, 0.999) < 1e-9, (j, rel.max())
+
+
+def test_iv_autograd_central_differences(fv):
+    """Against FP64 central differences of the GPU forward, h = 1e-6 relative
+    (absolute for r and q)."""
+    wl = W.bsm_diff(20_000, seed=44)
+    P = assemble_prices(wl)
+    base = dict(price=P, fs=wl.fs, K=wl.K, T=wl.T, r=wl.r, q=wl.q)
+    fl = dev(wl.flag, torch.int8)
+
+    def iv(**kw):
+        a = dict(base)
+        a.update(kw)
+        s, st = fv.implied_vol("bsm", dev(a["price"]), dev(a["fs"]), dev(a["K"]), dev(a["T"]),
+                               dev(a["r"]), flag=fl, q=dev(a["q"]))
+        return s.cpu().numpy()
+
+    ins = [dev(base[k], grad=True) for k in ("price", "fs", "K", "T", "r", "q")]
+    sig, st = fv.implied_vol_autograd("bsm", *ins[:5], flag=fl, q=ins[5])
+    sig.sum().backward()
+    ok = st.cpu().numpy() == 0
+    for j, k in enumerate(("price", "fs", "K", "T", "r", "q")):
+        x = base[k]
+        h = 1e-6 * (np.abs(x) if k in ("price", "fs", "K", "T") else np.ones_like(x))
+        fd = (iv(**{k: x + h}) - iv(**{k: x - h})) / (2 * h)
+        g = ins[j].grad.cpu().numpy()
+        rel = np.abs(g - fd) / np.maximum(np.abs(g), 1e-12)
+        # a shifted input can leave the solvable domain (price above its bound)
+        m = ok & np.isfinite(fd)
+        assert m.mean() > 0.99
+        assert np.median(rel[m]) < 1e-8 and np.quantile(rel[m], 0.99) < 1e-5, (k, rel[m].max())
+
+
+def test_composite_identity(fv):
+    """sigma -> price -> implied vol is the identity; its gradient is 1."""
+    wl = W.bsm_diff(100_000, seed=45)
+    fl = dev(wl.flag, torch.int8)
+    sig = dev(wl.sigma_true, grad=True)
+    p = fv.price_autograd("bsm", dev(wl.fs), dev(wl.K), dev(wl.T), dev(wl.r), sig, flag=fl,
+                          q=dev(wl.q))
+    iv, st = fv.implied_vol_autograd("bsm", p, dev(wl.fs), dev(wl.K), dev(wl.T), dev(wl.r),
+                                     flag=fl, q=dev(wl.q))
+    iv.sum().backward()
+    ok = st.cpu().numpy() == 0
+    g = sig.grad.cpu().numpy()
+    assert np.all(np.abs(g[ok] - 1.0) < 1e-9)
+    np.testing.assert_allclose(iv.detach().cpu().numpy()[ok], wl.sigma_true[ok], rtol=1e-6)
+
+
+def test_price_adjoint_matches_oracle_greeks(fv):
+    wl = W.bsm_diff(50_000, seed=46)
+    fl = dev(wl.flag, torch.int8)
+    ins = [dev(a, grad=True) for a in (wl.fs, wl.K, wl.T, wl.r, wl.q, wl.sigma_true)]
+    p = fv.price_autograd("bsm", ins[0], ins[1], ins[2], ins[3], ins[5], flag=fl, q=ins[4])
+    p.sum().backward()
+    g = oracle.greeks("bsm", wl.fs, wl.K, wl.T, wl.r, wl.q, wl.sigma_true, wl.flag)
+    for t, ref in ((ins[0], g["delta"]), (ins[2], -g["theta"]), (ins[3], g["rho"]),
+                   (ins[5], g["vega"])):
+        a = t.grad.cpu().numpy()
+        rel = np.abs(a - ref) / np.maximum(np.abs(ref), 1e-300)
+        assert np.quantile(rel, 0.999) < 1e-9

@@ -1,0 +1,311 @@
+"""GPU parity: the HIP library against the binary128 oracle, element by
+element, through the C ABI (via the thin Python binding)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_27210_amd import workloads as W
+
+from _helpers import (U, assemble_prices, boundary_ambiguous, compare_iv, cond_abs,
+                       forward_discount)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_27210_amd as fv
+    fv._native.load()
+    return fv
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def run_iv(fv, wl, P, solver, greeks=False):
+    q = dev(wl.q) if wl.model == "bsm" else None
+    out = fv.implied_vol(wl.model, dev(P), dev(wl.fs), dev(wl.K), dev(wl.T), dev(wl.r),
+                         flag=dev(wl.flag, torch.int8), q=q, solver=solver, greeks=greeks)
+    torch.cuda.synchronize()
+    return out
+
+
+def _report(name, res):
+    print("%s: ok=%d status_bad=%d value_bad=%d nan_bad=%d ambiguous=%d max err/tol=%.3f" % (
+        name, res["n_ok"], len(res["status_bad"]), len(res["value_bad"]), len(res["nan_bad"]),
+        res["ambiguous"], res["max_ratio"]), flush=True)
+
+
+@pytest.mark.parametrize("solver", ["lbr", "halley"])
+def test_bs_small_batch(fv, solver):
+    """Black-Scholes, 4,096 quotes (the small seeded workload), both solvers."""
+    wl = W.bs_small()
+    P = assemble_prices(wl)
+    sig, st = run_iv(fv, wl, P, solver)
+    res = compare_iv(wl.model, solver, P, wl.fs, wl.K, wl.T, wl.r, wl.q, wl.flag, host(sig),
+                     host(st))
+    _report("bs_small/" + solver, res)
+    assert len(res["status_bad"]) == 0
+    assert len(res["value_bad"]) == 0
+    assert len(res["nan_bad"]) == 0
+    assert res["n_ok"] > 3900
+
+
+@pytest.mark.parametrize("solver", ["lbr", "halley"])
+def test_bsm_wide_sample(fv, solver):
+    """Black-Scholes-Merton wide wings with 1% injected degenerate prices,
+    200,003 quotes (several thousand workgroups and a ragged tail)."""
+    wl = W.bsm_wide(200_003, seed=2)
+    P = assemble_prices(wl)
+    sig, st = run_iv(fv, wl, P, solver)
+    res = compare_iv(wl.model, solver, P, wl.fs, wl.K, wl.T, wl.r, wl.q, wl.flag, host(sig),
+                     host(st))
+    _report("bsm_wide/" + solver, res)
+    assert len(res["status_bad"]) == 0
+    assert len(res["value_bad"]) == 0
+    assert len(res["nan_bad"]) == 0
+    st_h = host(st)
+    # every injected quote is flagged, none silently solved
+    inj = wl.kind != W.KIND_CLEAN
+    amb = boundary_ambiguous(wl.model, P, wl.fs, wl.K, wl.T, wl.r, wl.q, wl.flag)
+    assert np.all((st_h[inj] != 0) | amb[inj])
+
+
+@pytest.mark.parametrize("model", ["black76", "bs", "bsm"])
+def test_models_and_flags(fv, model):
+    rng = np.random.default_rng(7)
+    n = 20_000
+    S = rng.uniform(20, 300, n)
+    T = np.exp(rng.uniform(np.log(1 / 365), np.log(5), n))
+    r = rng.uniform(-0.01, 0.08, n)
+    q = rng.uniform(0, 0.05, n) if model == "bsm" else np.zeros(n)
+    sig = np.exp(rng.uniform(np.log(0.02), np.log(2.5), n))
+    z = rng.uniform(-5, 5, n)
+    F, _ = forward_discount(model, S, T, r, q)
+    K = F * np.exp(-z * sig * np.sqrt(T))
+    flag = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+    wl = W.Flat(model, S, K, T, r, q, sig, flag)
+    P = assemble_prices(wl)
+    for solver in ("lbr", "halley"):
+        s, st = run_iv(fv, wl, P, solver)
+        res = compare_iv(model, solver, P, S, K, T, r, q, flag, host(s), host(st))
+        _report("%s/%s" % (model, solver), res)
+        assert len(res["status_bad"]) == 0 and len(res["value_bad"]) == 0
+        assert len(res["nan_bad"]) == 0
+
+
+def test_edge_cases(fv):
+    """Empty batch, single quote, at-the-money exactly, broadcast scalars,
+    invalid inputs, degenerate prices, extreme wings, huge and tiny vols."""
+    # n == 0 is a no-op
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    s0, st0 = fv.implied_vol("bsm", e, e, e, e, e, flag="c", q=e)
+    assert s0.numel() == 0
+    # exactly at the money (F == K) for Black-76, both flags, broadcast F/T/r
+    K = np.array([100.0, 100.0, 100.0, 100.0])
+    sig = np.array([0.01, 0.3, 1.5, 4.0])
+    T, r = 0.75, 0.02
+    for fl in (1, -1):
+        P = oracle.price("black76", 100.0, K, T, r, 0.0, sig, fl)
+        s, st = fv.implied_vol("black76", dev(P), 100.0, dev(K), T, r, flag=fl)
+        s, st = host(s), host(st)
+        assert np.all(st == 0)
+        np.testing.assert_allclose(s, sig, rtol=1e-12)
+    # invalid inputs and degenerate prices
+    P = np.array([np.nan, 5.0, 5.0, 5.0, 5.0, -1.0, 1e9, 0.0])
+    S = np.array([100.0, -1.0, 100.0, 100.0, 100.0, 100.0, 100.0, 100.0])
+    Kx = np.array([100.0, 100.0, 0.0, 100.0, 100.0, 100.0, 100.0, 150.0])
+    Tx = np.array([1.0, 1.0, 1.0, 0.0, np.inf, 1.0, 1.0, 1.0])
+    s, st = fv.implied_vol("bs", dev(P), dev(S), dev(Kx), dev(Tx), 0.01, flag="c")
+    s, st = host(s), host(st)
+    assert list(st) == [4, 4, 4, 4, 4, 2, 3, 1]
+    assert np.all(np.isnan(s[:7])) and s[7] == 0.0
+    # extreme wings and vol levels against the oracle
+    rng = np.random.default_rng(3)
+    n = 5000
+    h = -np.exp(rng.uniform(np.log(1e-4), np.log(30), n))
+    t = np.exp(rng.uniform(np.log(1e-4), np.log(5), n))
+    x = 2 * h * t
+    F = 100.0
+    Kw = F * np.exp(-x)
+    Tw = rng.uniform(0.01, 3, n)
+    sw = 2 * t / np.sqrt(Tw)
+    fl = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+    wl = W.Flat("black76", np.full(n, F), Kw, Tw, np.zeros(n), np.zeros(n), sw, fl)
+    P = assemble_prices(wl)
+    for solver in ("lbr", "halley"):
+        s, st = run_iv(fv, wl, P, solver)
+        res = compare_iv("black76", solver, P, wl.fs, Kw, Tw, 0.0 * Tw, 0.0 * Tw, fl, host(s),
+                         host(st))
+        _report("wings/" + solver, res)
+        assert len(res["status_bad"]) == 0 and len(res["value_bad"]) == 0
+
+
+def test_ragged_sizes_and_launch_shapes(fv):
+    """Sizes around wave and workgroup multiples under every launch shape give
+    bitwise the same per-quote results as the default shape (the per-quote
+    code does not depend on the shape), and the default agrees with the
+    oracle."""
+    wl_all = W.bsm_wide(70_000, seed=12, inject=0.01)
+    P_all = assemble_prices(wl_all)
+    ref = {}
+    for solver in ("lbr", "halley"):
+        s, st = run_iv(fv, wl_all, P_all, solver)
+        ref[solver] = (torch.nan_to_num(s, nan=-7.0), st)
+        res = compare_iv("bsm", solver, P_all, wl_all.fs, wl_all.K, wl_all.T, wl_all.r,
+                         wl_all.q, wl_all.flag, host(s), host(st))
+        assert len(res["status_bad"]) == 0 and len(res["value_bad"]) == 0
+    try:
+        for block, qpt in ((64, 1), (128, 2), (256, 4), (512, 3), (64, 16)):
+            fv.set_launch("iv_lbr", block, qpt)
+            fv.set_launch("iv_halley", block, qpt)
+            for n in sorted({1, 63, 64, 65, 257, block * qpt - 1, block * qpt + 1, 70_000}):
+                idx = np.arange(n)
+                wl = wl_all.take(idx)
+                for solver in ("lbr", "halley"):
+                    s, st = run_iv(fv, wl, P_all[idx], solver)
+                    rs, rst = ref[solver]
+                    assert torch.equal(torch.nan_to_num(s, nan=-7.0), rs[:n]), (block, qpt, n, solver)
+                    assert torch.equal(st, rst[:n]), (block, qpt, n, solver)
+    finally:
+        fv.set_launch("iv_lbr", 256, 1)
+        fv.set_launch("iv_halley", 256, 1)
+    # bad shapes are rejected
+    from paper_2604_27210_amd._native import FastvolError
+    with pytest.raises(FastvolError):
+        fv.set_launch("iv_lbr", 96, 1)
+    with pytest.raises(FastvolError):
+        fv.set_launch("iv_lbr", 1024, 1)
+
+
+@pytest.mark.parametrize("model", ["black76", "bs", "bsm"])
+def test_price_and_greeks(fv, model):
+    rng = np.random.default_rng(17)
+    n = 30_000
+    S = rng.uniform(20, 300, n)
+    T = np.exp(rng.uniform(np.log(1 / 365), np.log(5), n))
+    r = rng.uniform(-0.01, 0.08, n)
+    q = rng.uniform(0, 0.05, n) if model == "bsm" else np.zeros(n)
+    sig = np.exp(rng.uniform(np.log(0.02), np.log(2.5), n))
+    z = rng.uniform(-6, 6, n)
+    F, D = forward_discount(model, S, T, r, q)
+    K = F * np.exp(-z * sig * np.sqrt(T))
+    flag = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+    qd = dev(q) if model == "bsm" else None
+    p = host(fv.price(model, dev(S), dev(K), dev(T), dev(r), dev(sig), flag=dev(flag, torch.int8),
+                      q=qd))
+    po = oracle.price(model, S, K, T, r, q, sig, flag)
+    # first-order condition number of the price in its inputs (relative units)
+    g = oracle.greeks(model, S, K, T, r, q, sig, flag)
+    dPdK = -flag * D * _ncdf(flag * (np.log(F / K) / (sig * np.sqrt(T)) - 0.5 * sig * np.sqrt(T)))
+    cond = (np.abs(g["delta"] * S) + np.abs(dPdK * K) + np.abs(g["theta"] * T) +
+            np.abs(g["vega"] * sig) + np.abs(g["rho"] * r) + np.abs(S * T * q * D * F / S))
+    tol = 16 * U * (np.abs(po) + cond)
+    bad = ~(np.abs(p - po) <= tol)
+    assert bad.sum() == 0, (np.where(bad)[0][:5], p[bad][:5], po[bad][:5])
+    gd = fv.greeks(model, dev(S), dev(K), dev(T), dev(r), dev(sig), flag=dev(flag, torch.int8), q=qd)
+    for name in ("delta", "gamma", "vega", "theta", "rho"):
+        a = host(gd[name])
+        b = g[name]
+        scale = np.abs(b) + 1e-9 * np.max(np.abs(b))
+        rel = np.abs(a - b) / scale
+        assert np.quantile(rel, 0.999) < 1e-9 and np.max(rel) < 1e-6, (name, rel.max())
+
+
+def _ncdf(x):
+    from scipy.special import ndtr
+    return ndtr(x)
+
+
+def test_fused_greeks_match_separate_call(fv):
+    wl = W.bsm_diff(50_000, seed=4)
+    P = assemble_prices(wl)
+    sig, st, gk = run_iv(fv, wl, P, "lbr", greeks=True)
+    g2 = fv.greeks("bsm", dev(wl.fs), dev(wl.K), dev(wl.T), dev(wl.r), sig,
+                   flag=dev(wl.flag, torch.int8), q=dev(wl.q))
+    ok = host(st) == 0
+    for name in gk:
+        a, b = host(gk[name])[ok], host(g2[name])[ok]
+        rel = np.abs(a - b) / (np.abs(b) + 1e-12)
+        assert np.quantile(rel, 0.999) < 1e-10, name
+
+
+def test_backward_matches_oracle_gradient(fv):
+    wl = W.bsm_diff(100_000, seed=4)
+    P = assemble_prices(wl)
+    sig, st = run_iv(fv, wl, P, "lbr")
+    w = dev(wl.extra["w"])
+    gr = fv.implied_vol_backward("bsm", dev(P), dev(wl.fs), dev(wl.K), dev(wl.T), dev(wl.r), sig,
+                                 w, flag=dev(wl.flag, torch.int8), q=dev(wl.q))
+    go = oracle.iv_grad("bsm", P, wl.fs, wl.K, wl.T, wl.r, wl.q, wl.flag)
+    ok = (host(st) == 0) & np.all(np.isfinite(go), 1)
+    wh = wl.extra["w"]
+    for j, name in enumerate(("price", "fs", "K", "T", "r", "q")):
+        a = host(gr[name])[ok]
+        b = (wh[:, None] * go)[ok, j]
+        rel = np.abs(a - b) / (np.abs(b) + 1e-300)
+        assert np.quantile(rel, 0.999) < 1e-9 and np.median(rel) < 1e-12, (name, rel.max())
+
+
+def test_chains_match_flat_and_oracle(fv):
+    ch = W.b76_chains(60, seed=3)
+    flat = ch.flatten()
+    P = oracle.price("black76", flat.fs, flat.K, flat.T, flat.r, 0.0, flat.sigma_true, flat.flag)
+    for solver in ("lbr", "halley"):
+        for block, qpt in ((256, 1), (128, 4), (512, 2)):
+            fv.set_launch("chains", block, qpt)
+            sc, stc = fv.implied_vol_chains(
+                dev(ch.chain_mat_off, torch.int64), dev(ch.mat_quote_off, torch.int64), dev(ch.F),
+                dev(ch.r), dev(ch.T), dev(P), dev(ch.K), dev(ch.flag, torch.int8), solver=solver)
+            sf, stf = fv.implied_vol("black76", dev(P), dev(flat.fs), dev(flat.K), dev(flat.T),
+                                     dev(flat.r), flag=dev(flat.flag, torch.int8), solver=solver)
+            torch.cuda.synchronize()
+            if solver == "lbr":
+                # same per-quote code path: bitwise identical to the flat kernel
+                assert torch.equal(stc, stf)
+                assert torch.equal(torch.nan_to_num(sc, nan=-1.0), torch.nan_to_num(sf, nan=-1.0))
+            res = compare_iv("black76", solver, P, flat.fs, flat.K, flat.T, flat.r, 0.0 * flat.T,
+                             flat.flag, host(sc), host(stc))
+            assert len(res["status_bad"]) == 0 and len(res["value_bad"]) == 0
+    fv.set_launch("chains", 256, 1)
+
+
+def test_normalised_black_matches_oracle(fv):
+    rng = np.random.default_rng(23)
+    n = 100_000
+    h = -np.exp(rng.uniform(np.log(1e-3), np.log(36), n))
+    t = np.exp(rng.uniform(np.log(1e-5), np.log(6), n))
+    x = 2 * h * t * np.where(rng.random(n) < 0.5, 1, -1)
+    s = 2 * t
+    fl = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+    b = host(fv.normalised_black(dev(x), dev(s), dev(fl, torch.int8)))
+    bo = oracle.normalised_black(x, s, fl)
+    ok = bo > 1e-300
+    # condition number of b in x (the kernel rounds h = x/s): |x db/dx| / b
+    hh, tt = x / s, s / 2
+    from scipy.special import ndtr
+    bx = 0.5 * (np.exp(x / 2) * ndtr(fl * (hh + tt)) + np.exp(-x / 2) * ndtr(fl * (hh - tt)))
+    cond = np.abs(x * bx) / np.maximum(bo, 1e-300)
+    rel = np.abs(b - bo) / np.maximum(bo, 1e-300)
+    bad = ok & ~(rel <= 64 * U * (1 + cond) + 1e-15)
+    assert bad.sum() == 0, (np.where(bad)[0][:5], rel[bad][:5], cond[bad][:5])
+
+
+def test_invalid_calls_raise(fv):
+    d = dev(np.ones(4))
+    from paper_2604_27210_amd._native import FastvolError
+    with pytest.raises(FastvolError):
+        fv.implied_vol(7, d, d, d, d, d)
+    with pytest.raises(FastvolError):
+        fv.implied_vol("bsm", d, d, d, d, d, solver=5)
+    with pytest.raises((ValueError, TypeError)):
+        fv.implied_vol("bsm", d, d, d.float(), d, d)
