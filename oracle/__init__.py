@@ -24,7 +24,7 @@ _LIB_PATH = os.path.join(_OUT_DIR, "libfv_oracle.so")
 
 MODELS = {"black76": 0, "bs": 1, "bsm": 2}
 # status numbering of the oracle (mirrors the documented per-quote codes)
-ST_OK, ST_AT, ST_BELOW, ST_ABOVE, ST_INVALID, ST_NO_EXACT_ROOT = 0, 1, 2, 3, 4, 8
+ST_OK, ST_AT, ST_BELOW, ST_ABOVE, ST_INVALID, ST_NO_EXACT_ROOT, ST_ROOT_CAP = 0, 1, 2, 3, 4, 8, 9
 
 _lib = None
 

@@ -50,7 +50,9 @@ enum {
     /* binary64 comparisons say "solvable" but in exact arithmetic the price
      * sits on or outside the no-arbitrage bounds, so no finite positive root
      * exists: a boundary-ambiguous quote */
-    ORC_NO_EXACT_ROOT = 8
+    ORC_NO_EXACT_ROOT = 8,
+    /* the root iteration hit its cap (a defect of this file if it occurs) */
+    ORC_ROOT_CAP = 9
 };
 
 static const qr Q_SQRT2 = 1.41421356237309504880168872420969807856967Q;
@@ -211,7 +213,8 @@ static qr q_vega(const qin *a, qr sigma)
 }
 
 /* Returns the root; *ok = 0 if no finite positive root exists in exact
- * arithmetic (price on or outside the bounds). */
+ * arithmetic (price on or outside the bounds), *ok = -1 if the iteration
+ * hit its cap (never expected; the tests assert it does not happen). */
 static qr q_implied_vol(const qin *a, qr P, int *ok)
 {
     *ok = 1;
@@ -225,17 +228,22 @@ static qr q_implied_vol(const qin *a, qr P, int *ok)
         if (++k > 60) { *ok = 0; return 0; }
     }
     qr sig = (lo > 0) ? 0.5Q * (lo + hi) : 0.5Q * hi;
-    qr prev_step = hi;
-    for (int it = 0; it < 400; ++it) {
+    /* A Newton step is taken only if it stays inside the bracket and is at
+     * most half as long as the step before the previous one; otherwise the
+     * bracket is bisected.  So the iterate cannot crawl (Newton from the
+     * convex side of a deep out-of-the-money price moves by ~1/h^2 relative
+     * per step) and the bracket keeps shrinking. */
+    qr step1 = hi, step2 = hi;
+    for (int it = 0; it < 4000; ++it) {
         qr f = q_price(a, sig) - P;
         if (f == 0) return sig;
         if (f < 0) lo = sig; else hi = sig;
         qr v = q_vega(a, sig);
-        qr nxt;
+        qr nxt = 0;
         int newton_ok = 0;
         if (v > 0) {
             nxt = sig - f / v;
-            if (nxt > lo && nxt < hi) newton_ok = 1;
+            if (nxt > lo && nxt < hi && fabsq(nxt - sig) <= 0.5Q * step2) newton_ok = 1;
         }
         if (!newton_ok) {
             /* bisection: geometric when the bracket spans more than 4x */
@@ -244,16 +252,13 @@ static qr q_implied_vol(const qin *a, qr P, int *ok)
             else nxt = 0.5Q * (lo + hi);
         }
         qr step = fabsq(nxt - sig);
+        step2 = step1;
+        step1 = step;
         sig = nxt;
-        if (newton_ok) {
-            if (step <= 1e-31Q * sig) return sig;
-            /* stagnation at the binary128 noise floor of an ill-conditioned
-             * quote: the steps stop shrinking */
-            if (step <= 1e-24Q * sig && step >= prev_step) return sig;
-            prev_step = step;
-        }
+        if (newton_ok && step <= 1e-31Q * sig) return sig;
         if (hi - lo <= 1e-31Q * hi) return 0.5Q * (lo + hi);
     }
+    *ok = -1;
     return sig;
 }
 
@@ -351,11 +356,11 @@ void orc_implied_vol_n(int model, int64_t n, const double *price, const double *
             fill_in(&a, model, fs[i], K[i], T[i], r[i], q[i], flag[i]);
             int ok;
             qr s = q_implied_vol(&a, price[i], &ok);
-            if (ok) {
+            if (ok > 0) {
                 out = (double)s;
                 outlo = (double)(s - (qr)out);
             } else {
-                st = ORC_NO_EXACT_ROOT;
+                st = ok == 0 ? ORC_NO_EXACT_ROOT : ORC_ROOT_CAP;
             }
         }
         sigma[i] = out;
@@ -383,7 +388,7 @@ void orc_iv_grad_n(int model, int64_t n, const double *price, const double *fs,
         fill_in(&a, model, fs[i], K[i], T[i], r[i], q[i], flag[i]);
         int ok;
         qr s = q_implied_vol(&a, price[i], &ok);
-        if (!ok) continue;
+        if (ok <= 0) continue;
         qr v = q_vega(&a, s);
         qr dP[5];
         q_price_partials(&a, s, dP);

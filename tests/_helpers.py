@@ -86,6 +86,7 @@ def compare_iv(model, solver, P, fs, K, T, r, q, flag, sig, st):
     the indices of failures (status mismatches outside the boundary-ambiguous
     set, and value mismatches beyond the tolerance)."""
     so, sto = oracle.implied_vol(model, P, fs, K, T, r, q, flag)
+    assert not np.any(sto == oracle.ST_ROOT_CAP), "oracle root iteration hit its cap"
     sto = sto.copy()
     amb = boundary_ambiguous(model, P, fs, K, T, r, q, flag) | (sto == oracle.ST_NO_EXACT_ROOT)
     st_bad = (sto != st) & ~amb

@@ -240,6 +240,30 @@ def test_iv_round_trip_and_parity(orc, model):
     np.testing.assert_allclose(ivc[both], ivp[both], rtol=2e-13)
 
 
+def test_iv_round_trip_deep_wings(orc):
+    """Deep out-of-the-money quotes (h = ln(F/K)/s down to -36, prices far
+    below 1e-100): the root still re-prices to the input price, and the
+    iteration never hits its cap."""
+    rng = np.random.default_rng(65)
+    n = 3000
+    h = -np.exp(rng.uniform(np.log(1e-3), np.log(36), n))
+    t = np.exp(rng.uniform(np.log(1e-4), np.log(4), n))
+    F = 100.0
+    K = F * np.exp(-2 * h * t)
+    T = rng.uniform(0.01, 3, n)
+    sig = 2 * t / np.sqrt(T)
+    flag = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+    P = orc.price("black76", F, K, T, 0.0, 0.0, sig, flag)
+    iv, st = orc.implied_vol("black76", P, F, K, T, 0.0, 0.0, flag)
+    assert not np.any(st == orc.ST_ROOT_CAP)
+    ok = st == 0
+    assert ok.mean() > 0.9
+    P2 = orc.price("black76", F, K[ok], T[ok], 0.0, 0.0, iv[ok], flag[ok])
+    # re-pricing error is the price's own sensitivity to one ulp of sigma
+    vega = orc.greeks("black76", F, K[ok], T[ok], 0.0, 0.0, iv[ok], flag[ok])["vega"]
+    assert np.all(np.abs(P2 - P[ok]) <= 4 * np.spacing(P[ok]) + 2 * vega * np.spacing(iv[ok]))
+
+
 def test_iv_atm_closed_form_erfinv(orc):
     # Black-76, F = K: P = D F erf(s / (2 sqrt 2))  =>  s = 2 sqrt(2) erfinv(P/(D F))
     rng = np.random.default_rng(71)
