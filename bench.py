@@ -43,6 +43,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=200_000,
                     help="quotes of the workload the oracle solves for the CPU baseline")
+    ap.add_argument("--census", action="store_true",
+                    help="instead of the bench: group the quotes by LBR path (fv_lbr_trace), "
+                         "then run the LBR kernel once on the workload as generated and once "
+                         "with quotes sorted by path, so that FP64 instruction counters "
+                         "(rocprofv3 --pmc) of the sorted launch give the algorithmic work")
     return ap.parse_args()
 
 
@@ -84,11 +89,41 @@ def cpu_baseline(wl, P, sample):
                       "root, OpenMP over %d threads, %.2f s wall" % (sample, oracle.num_threads(), dt)}
 
 
+def census(fv, torch, P, S, K, T, r, q, flag):
+    code = fv.lbr_trace("bsm", P, S, K, T, r, flag=flag, q=q)
+    order = torch.argsort(code.to(torch.int64))
+    cs = code[order]
+    args = [x.index_select(0, order).contiguous() for x in (P, S, K, T, r, q)]
+    fl = flag.index_select(0, order).contiguous()
+    times = {}
+    for label, ins, f in (("as_generated", (P, S, K, T, r, q), flag), ("sorted_by_path", args, fl)):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fv.implied_vol("bsm", ins[0], ins[1], ins[2], ins[3], ins[4], flag=f, q=ins[5], solver="lbr")
+        e1.record()
+        torch.cuda.synchronize()
+        times[label] = e0.elapsed_time(e1)
+    c = cs.cpu().numpy().astype(np.uint32)
+    solved = c != 0xFFFFFFFF
+    region = np.bincount(c[solved] & 3, minlength=4) / solved.sum()
+    steps = np.bincount((c[solved] >> 2) & 3, minlength=3) / solved.sum()
+    n_paths = len(np.unique(c[solved]))
+    print(json.dumps({"census": True, "n": int(P.numel()), "solved": int(solved.sum()),
+                      "distinct_paths": n_paths,
+                      "region_fraction_R1_R4": region.round(4).tolist(),
+                      "steps_fraction_2_3_4": steps.round(5).tolist(),
+                      "ms_as_generated": times["as_generated"],
+                      "ms_sorted_by_path": times["sorted_by_path"],
+                      "launch_order": ["as_generated", "sorted_by_path"]}), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(quotes are independent; see DESIGN.md for how it would shard)", file=sys.stderr)
+              "(quotes are independent, so a multi-GPU run would shard the batch by contiguous "
+              "index ranges with no exchange)", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2604_27210_amd as fv
@@ -96,6 +131,9 @@ def main():
     torch.cuda.init()
     wl, P, S, K, T, r, q, flag = make_inputs(a.n, torch, fv)
     stream = torch.cuda.current_stream()
+    if a.census:
+        census(fv, torch, P, S, K, T, r, q, flag)
+        return
 
     def step():
         return fv.implied_vol("bsm", P, S, K, T, r, flag=flag, q=q, solver=a.solver)

@@ -156,12 +156,60 @@ int fv_price_backward(int model, const fv_quotes *q, fv_arg sigma, const double 
 int fv_implied_vol_chains(int solver, const fv_chains *c, double *sigma_out,
                           uint8_t *status_out, void *stream);
 
+/* Calibration problem: per-maturity SVI smiles on ragged Black-76 chains,
+ * fitted through the differentiable implied volatility (the paper's
+ * section 1 motivation -- IV inside calibration pipelines -- with the
+ * autograd-friendly IV of section 3).  Per maturity m the raw parameters are
+ * theta[5m .. 5m+4] = (a, b~, rho~, mu, s~) with b = softplus(b~),
+ * rho = tanh(rho~), s = softplus(s~), total variance
+ *   w(k) = a + b (rho (k - mu) + sqrt((k - mu)^2 + s^2)),  k = ln(K/F),
+ * sigma_SVI = sqrt(w/T).  The loss is
+ *   L = (1/n_quotes) sum_i (IV(P_Black76(sigma_SVI,i)) - iv_target_i)^2,
+ * quotes with w <= 1e-10, a non-solvable price or a non-finite target
+ * contribute nothing.  chains.price is not read; all arrays are device
+ * arrays. */
+typedef struct {
+    fv_chains chains;
+    const double *iv_target;             /* [n_quotes] */
+    double lr, beta1, beta2, eps;        /* Adam hyper-parameters */
+} fv_svi_problem;
+
+/* One Adam step of the calibration, as three launches on `stream` that
+ * allocate nothing and never synchronise (capturable in a hipGraph):
+ * per-maturity gradients (one workgroup per maturity; SVI -> Black-76 price
+ * -> LBR implied volatility -> implicit-function adjoint, reduced in a fixed
+ * order, so results are bitwise reproducible), the Adam update, and the loss.
+ *   theta, adam_m, adam_v: [5 n_maturities] in/out (moments start at 0);
+ *   step: one device int64 (Adam's step count t, read then incremented);
+ *   grad: [5 n_maturities] out, scratch: gradient at the pre-update theta;
+ *   loss_parts: [n_maturities] out, scratch;
+ *   loss: [loss_len] history (may be NULL): loss[t] receives the loss at the
+ *   pre-update theta of step t (t read from *step; nothing written when
+ *   t >= loss_len).  A replayed graph thus records every step's loss. */
+int fv_svi_adam_step(const fv_svi_problem *p, double *theta, double *adam_m, double *adam_v,
+                     int64_t *step, double *grad, double *loss_parts, double *loss,
+                     int64_t loss_len, void *stream);
+
+/* sigma_SVI of every quote at parameters theta [5 n_maturities];
+ * sigma_out [n_quotes] (NaN where w <= 0). */
+int fv_svi_vols(const fv_svi_problem *p, const double *theta, double *sigma_out, void *stream);
+
 /* Normalised Black function b(x, s, theta) (the evaluator underneath every
  * entry point): theta [e^{x/2} Phi(theta(x/s + s/2)) - e^{-x/2}
  * Phi(theta(x/s - s/2))].  x, s: device arrays [n] (s >= 0); flag: device
  * int8 [n] or NULL for calls.  out: [n]. */
 int fv_normalised_black(int64_t n, const double *x, const double *s, const int8_t *flag,
                         double *out, void *stream);
+
+/* Diagnostic: the path each quote takes through the LBR solver, as
+ * fv_implied_vol(..., FV_SOLVER_LBR, ...) solves it.  path_out: uint32 [n];
+ * bits 0-1 guess region (0..3 = lower map / lower interior / upper interior /
+ * upper map), bits 2-3 Householder(3) steps minus 2, bits 4-5 and 6-7 the
+ * normalised-Black evaluation form at the two boundary points, from bit 8
+ * two bits per step (forms: 0 asymptotic, 1 small-t, 2 erfcx, 3 erfcx
+ * complement).  0xFFFFFFFF for quotes whose status is not FV_Q_OK.  Used to
+ * group quotes by path, e.g. to measure divergence. */
+int fv_lbr_trace(int model, const fv_quotes *q, uint32_t *path_out, void *stream);
 
 /* Launch-shape control.  fv_set_launch(kernel, block, quotes_per_thread)
  * overrides the launch shape of one kernel family (FV_KERNEL_*); block must

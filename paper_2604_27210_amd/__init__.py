@@ -10,7 +10,7 @@ The native library is loaded lazily, on the first call that needs it.
 from . import _native  # noqa: F401
 
 __all__ = ["price", "implied_vol", "greeks", "implied_vol_backward", "implied_vol_chains",
-           "price_backward", "price_autograd",
+           "price_backward", "price_autograd", "lbr_trace",
            "normalised_black", "set_launch", "get_launch", "autotune", "version",
            "IVFunction", "implied_vol_autograd"]
 
@@ -18,7 +18,7 @@ __all__ = ["price", "implied_vol", "greeks", "implied_vol_backward", "implied_vo
 def __getattr__(name):
     if name in ("price", "implied_vol", "greeks", "implied_vol_backward", "implied_vol_chains",
                 "normalised_black", "set_launch", "get_launch", "autotune", "version",
-                "price_backward"):
+                "price_backward", "lbr_trace"):
         from . import api
         return getattr(api, name)
     if name in ("IVFunction", "implied_vol_autograd", "PriceFunction", "price_autograd"):

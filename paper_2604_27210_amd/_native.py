@@ -11,7 +11,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "_build", "libfastvol.so")
+# FASTVOL_LIBRARY may name another build of the same library (e.g. one
+# compiled with different register-allocation targets)
+LIB_PATH = os.environ.get("FASTVOL_LIBRARY") or os.path.join(HERE, "_build", "libfastvol.so")
 
 FV_OK = 0
 FV_E_INVALID_ARG = -1
@@ -46,9 +48,14 @@ class FvChains(ctypes.Structure):
                 ("price", ctypes.c_void_p), ("K", ctypes.c_void_p), ("flag", ctypes.c_void_p)]
 
 
+class FvSviProblem(ctypes.Structure):
+    _fields_ = [("chains", FvChains), ("iv_target", ctypes.c_void_p), ("lr", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double)]
+
+
 EXPORTS = ["fv_price", "fv_implied_vol", "fv_greeks", "fv_implied_vol_backward", "fv_price_backward",
-           "fv_implied_vol_chains", "fv_normalised_black", "fv_set_launch", "fv_get_launch",
-           "fv_autotune", "fv_last_error", "fv_version"]
+           "fv_implied_vol_chains", "fv_normalised_black", "fv_lbr_trace", "fv_set_launch", "fv_get_launch",
+           "fv_autotune", "fv_svi_adam_step", "fv_svi_vols", "fv_last_error", "fv_version"]
 
 _lib = None
 
@@ -76,6 +83,9 @@ def load():
     lib.fv_price_backward.argtypes = [I, P(FvQuotes), FvArg, V, V, V, V, V, V, V, V]
     lib.fv_implied_vol_chains.argtypes = [I, P(FvChains), V, V, V]
     lib.fv_normalised_black.argtypes = [I64, V, V, V, V, V]
+    lib.fv_lbr_trace.argtypes = [I, P(FvQuotes), V, V]
+    lib.fv_svi_adam_step.argtypes = [P(FvSviProblem), V, V, V, V, V, V, V, I64, V]
+    lib.fv_svi_vols.argtypes = [P(FvSviProblem), V, V, V]
     lib.fv_set_launch.argtypes = [I, I, I]
     lib.fv_get_launch.argtypes = [I, P(I), P(I)]
     lib.fv_autotune.argtypes = [I, I, I64, V]

@@ -215,6 +215,16 @@ def normalised_black(x, s, flag=None, stream=None) -> torch.Tensor:
     return out
 
 
+def lbr_trace(model, price, fs, K, T, r, flag="c", q=None, stream=None) -> torch.Tensor:
+    """Per-quote path code of the LBR solver (see fv_lbr_trace)."""
+    b = _Batch(price=price, fs=fs, K=K, T=T, r=r, q=q, flag=flag)
+    qs = b.quotes(price, fs, K, T, r, q, flag)
+    out = torch.empty(b.n, dtype=torch.int32, device=b.device)
+    N.check(N.load().fv_lbr_trace(_model(model), ctypes.byref(qs), _ptr(out),
+                                  ctypes.c_void_p(_stream_ptr(stream))), "fv_lbr_trace")
+    return out
+
+
 def set_launch(kernel, block: int, quotes_per_thread: int) -> None:
     k = N.KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     N.check(N.load().fv_set_launch(k, int(block), int(quotes_per_thread)), "fv_set_launch")

@@ -14,8 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libfastvol.so")
-SOURCES = [os.path.join(CSRC, "fv_kernels.hip")]
-HEADERS = ["fv_math.h", "fv_lbr.h", "fv_quote.h", "fv_coeffs.h"]
+SOURCES = [os.path.join(CSRC, "fv_kernels.hip"), os.path.join(CSRC, "fv_calib.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -30,9 +29,10 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, extra=None) -> str:
-    os.makedirs(OUT_DIR, exist_ok=True)
-    tmp = LIB + ".tmp%d" % os.getpid()
+def build(verbose: bool = False, extra=None, out: str = None) -> str:
+    lib = out or LIB
+    os.makedirs(os.path.dirname(lib), exist_ok=True)
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [HIPCC] + FLAGS + list(extra or []) + ["-I", os.path.join(HERE, "..", "include")] \
         + SOURCES + ["-o", tmp]
     if verbose:
@@ -44,8 +44,8 @@ def build(verbose: bool = False, extra=None) -> str:
         raise RuntimeError("hipcc failed:\n" + msgs)
     if verbose and msgs.strip():
         print(msgs)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -20,7 +20,22 @@
 #include <vector>
 
 #include "../../include/fastvol.h"
+#include "fv_host.h"
 #include "fv_quote.h"
+
+// Error state shared by every entry point of the library (fv_host.h).
+namespace fvh {
+thread_local std::string g_last_error;
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+int launched(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(FV_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return FV_OK;
+}
+}  // namespace fvh
 
 namespace {
 
@@ -52,9 +67,13 @@ struct GreekOut {
 // LBR iteration policy: two Householder(3) steps always; a third (and at most
 // a fourth) only while the previous step still moved s by more than 1e-6
 // relative, i.e. only in waves that hold such a lane.
-// Largest workgroup the kernels are compiled for: 8 waves per workgroup lets
-// the register allocator use up to 256 VGPRs per lane (2 waves per SIMD).
+// Largest workgroup the kernels are compiled for (8 waves).
 constexpr int kMaxBlock = 512;
+// Minimum resident waves per SIMD the solver kernels are register-allocated
+// for (2: up to 256 VGPRs, 3: 168, 4: 128).
+#ifndef FV_SOLVER_WAVES_PER_EU
+#define FV_SOLVER_WAVES_PER_EU 2
+#endif
 
 constexpr int kLbrMinSteps = 2;
 constexpr int kLbrMaxSteps = 4;
@@ -87,7 +106,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_price(KQuotes q, fv_arg sigma, do
 
 // ------------------------------------------------------------- IV: LBR
 template <int MODEL, bool GREEKS>
-__global__ __launch_bounds__(kMaxBlock) void k_iv_lbr(KQuotes q, double* __restrict__ sig_out, uint8_t* __restrict__ st_out,
+__global__ __launch_bounds__(kMaxBlock)
+__attribute__((amdgpu_waves_per_eu(FV_SOLVER_WAVES_PER_EU))) void k_iv_lbr(KQuotes q, double* __restrict__ sig_out, uint8_t* __restrict__ st_out,
                          GreekOut g, int qpt) {
   const int64_t base = (int64_t)blockIdx.x * blockDim.x * qpt + threadIdx.x;
   for (int k = 0; k < qpt; ++k) {
@@ -124,6 +144,28 @@ __global__ __launch_bounds__(kMaxBlock) void k_iv_lbr(KQuotes q, double* __restr
   }
 }
 
+// Diagnostic twin of k_iv_lbr: the same per-quote solve, recording the path
+// each quote takes (guess region, evaluation forms, number of steps).
+template <int MODEL>
+__global__ __launch_bounds__(kMaxBlock) void k_lbr_trace(KQuotes q, uint32_t* __restrict__ out,
+                                                         int qpt) {
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x * qpt + threadIdx.x;
+  for (int k = 0; k < qpt; ++k) {
+    const int64_t i = base + (int64_t)k * blockDim.x;
+    if (i >= q.n) return;
+    const double P = ld(q.price, i), fs = ld(q.fs, i), K = ld(q.K, i), T = ld(q.T, i),
+                 r = ld(q.r, i);
+    const double qy = MODEL == fv::kBlackScholesMerton ? ld(q.q, i) : 0.0;
+    const Reduced rd = fv::reduce_quote(MODEL, P, fs, K, T, r, qy, ldflag(q, i));
+    uint32_t code = 0xFFFFFFFFu;  // not solved (status != OK)
+    if (rd.status == fv::kQOk) {
+      code = 0;
+      fv::lbr_solve(rd.x, rd.beta, kLbrMinSteps, kLbrMaxSteps, kLbrStepTol, &code);
+    }
+    out[i] = code;
+  }
+}
+
 // ------------------------------------------------------------- IV: Halley
 // LDS queue entry of a lane that failed the convergence check.
 struct Pending {
@@ -137,7 +179,8 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 }
 
 template <int MODEL, bool GREEKS>
-__global__ __launch_bounds__(kMaxBlock) void k_iv_halley(KQuotes q, double* __restrict__ sig_out,
+__global__ __launch_bounds__(kMaxBlock)
+__attribute__((amdgpu_waves_per_eu(FV_SOLVER_WAVES_PER_EU))) void k_iv_halley(KQuotes q, double* __restrict__ sig_out,
                             uint8_t* __restrict__ st_out, GreekOut g, int qpt) {
   extern __shared__ unsigned char smem_raw[];
   Pending* queue = reinterpret_cast<Pending*>(smem_raw);
@@ -351,7 +394,8 @@ __device__ __forceinline__ int64_t upper_index(const int64_t* __restrict__ off, 
 // search over the CSR offsets; the other lanes walk forward from it (a
 // maturity holds at least one quote, so the walk is short).
 template <int SOLVER>
-__global__ __launch_bounds__(kMaxBlock) void k_iv_chains(KChains c, double* __restrict__ sig_out,
+__global__ __launch_bounds__(kMaxBlock)
+__attribute__((amdgpu_waves_per_eu(FV_SOLVER_WAVES_PER_EU))) void k_iv_chains(KChains c, double* __restrict__ sig_out,
                             uint8_t* __restrict__ st_out, int qpt) {
   const int64_t chunk = (int64_t)blockDim.x * qpt;
   const int64_t n_chunks = (c.n + chunk - 1) / chunk;
@@ -411,17 +455,76 @@ __global__ void k_normalised_black(int64_t n, const double* __restrict__ x,
   const double bmax = exp(0.5 * xo);
   const fv::NBlack nb = fv::normalised_black(xo, si, bmax);
   double b = nb.b;
-  if (th * xi > 0.0) b += th * (exp(0.5 * xi) - exp(-0.5 * xi));
+  // in the money: add the intrinsic th (e^{x/2} - e^{-x/2}) = th 2 sinh(x/2),
+  // from expm1 so that small |x| keeps its relative precision
+  if (th * xi > 0.0) b += th * (expm1(0.5 * xi) - expm1(-0.5 * xi));
   out[i] = b;
 }
 
-// ------------------------------------------------------------- host side
-thread_local std::string g_last_error;
-
-int fail(int code, const std::string& msg) {
-  g_last_error = msg;
-  return code;
+// ------------------------------------------------------------- autotune inputs
+// Synthetic in-range quotes for timing candidate launch shapes: a
+// counter-based generator (the splitmix64 output function of Steele, Lea &
+// Flood, OOPSLA 2014) drives the same distributions as the wide-wing
+// Black-Scholes-Merton workload (z~U[-6,6], sigma~logU[0.01,3],
+// T~logU[1/365,5], r~U[-0.01,0.08], q~U[0,0.05], S = 100).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
 }
+__device__ __forceinline__ double unif(uint64_t key) {
+  return (double)(splitmix64(key) >> 11) * 0x1.0p-53;
+}
+
+__global__ void k_tune_quotes(int64_t n, double* S, double* K, double* T, double* r,
+                              double* q, double* sig, int8_t* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t b = (uint64_t)i * 8;
+  const double z = -6.0 + 12.0 * unif(b);
+  const double sg = exp(log(0.01) + unif(b + 1) * log(300.0));
+  const double Ti = exp(log(1.0 / 365.0) + unif(b + 2) * log(5.0 * 365.0));
+  const double ri = -0.01 + 0.09 * unif(b + 3);
+  const double qi = 0.05 * unif(b + 4);
+  const double F = 100.0 * exp((ri - qi) * Ti);
+  S[i] = 100.0;
+  K[i] = F * exp(-z * sg * sqrt(Ti));
+  T[i] = Ti;
+  r[i] = ri;
+  q[i] = qi;
+  sig[i] = sg;
+  flag[i] = unif(b + 5) < 0.5 ? 1 : -1;
+}
+
+// Ragged structure for timing the chain kernel: every maturity holds
+// `per_mat` quotes and every chain `mats` maturities; per-chain F = 100 and
+// r, per-maturity T taken from the flat synthetic quotes.
+__global__ void k_tune_chains(int64_t n_chains, int64_t n_mat, int64_t n, int mats,
+                              int per_mat, const double* Tq, const double* rq, int64_t* cmo,
+                              int64_t* mqo, double* F, double* r, double* T) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= n_chains) cmo[i] = i * mats;
+  if (i <= n_mat) mqo[i] = i * per_mat;
+  if (i < n_chains) {
+    F[i] = 100.0;
+    r[i] = rq[i * mats * per_mat];
+  }
+  if (i < n_mat) T[i] = Tq[i * per_mat];
+  (void)n;
+}
+
+// Per-quote T and r of the ragged structure (to price its quotes).
+__global__ void k_tune_expand(int64_t n, int mats, int per_mat, const double* cT,
+                              const double* cr, double* Te, double* re) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Te[i] = cT[i / per_mat];
+  re[i] = cr[i / ((int64_t)per_mat * mats)];
+}
+
+// ------------------------------------------------------------- host side
+int fail(int code, const std::string& msg) { return fvh::fail(code, msg); }
 
 struct LaunchShape {
   int block, qpt;
@@ -468,11 +571,7 @@ dim3 grid_for(int64_t n, const LaunchShape& sh) {
   return dim3((unsigned)((n + per - 1) / per));
 }
 
-int launched(const char* what) {
-  const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(FV_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
-  return FV_OK;
-}
+int launched(const char* what) { return fvh::launched(what); }
 
 int device_cus() {
   int dev = 0, cus = 0;
@@ -490,7 +589,7 @@ extern "C" {
 
 int fv_version(void) { return FV_ABI_VERSION; }
 
-const char* fv_last_error(void) { return g_last_error.c_str(); }
+const char* fv_last_error(void) { return fvh::g_last_error.c_str(); }
 
 int fv_set_launch(int kernel, int block, int qpt) {
   if (kernel < 0 || kernel >= FV_KERNEL_COUNT) return fail(FV_E_INVALID_ARG, "kernel id");
@@ -635,6 +734,23 @@ int fv_price_backward(int model, const fv_quotes* q, fv_arg sigma, const double*
   return launched("fv_price_backward");
 }
 
+int fv_lbr_trace(int model, const fv_quotes* q, uint32_t* path_out, void* stream) {
+  int rc = check_quotes(model, q);
+  if (rc) return rc;
+  if (q->n == 0) return FV_OK;
+  if (!path_out) return fail(FV_E_INVALID_ARG, "path_out is NULL");
+  const LaunchShape sh = g_shape[FV_KERNEL_IV_LBR];
+  const KQuotes k = to_k(q);
+  hipStream_t s = (hipStream_t)stream;
+  const dim3 grid = grid_for(q->n, sh), block(sh.block);
+  switch (model) {
+    case FV_MODEL_BLACK76: k_lbr_trace<0><<<grid, block, 0, s>>>(k, path_out, sh.qpt); break;
+    case FV_MODEL_BLACK_SCHOLES: k_lbr_trace<1><<<grid, block, 0, s>>>(k, path_out, sh.qpt); break;
+    default: k_lbr_trace<2><<<grid, block, 0, s>>>(k, path_out, sh.qpt); break;
+  }
+  return launched("fv_lbr_trace");
+}
+
 int fv_implied_vol_chains(int solver, const fv_chains* c, double* sigma_out,
                           uint8_t* status_out, void* stream) {
   if (!c) return fail(FV_E_INVALID_ARG, "chains pointer is NULL");
@@ -685,8 +801,143 @@ int fv_normalised_black(int64_t n, const double* x, const double* s, const int8_
 }
 
 int fv_autotune(int kernel, int model, int64_t n_hint, void* stream) {
-  (void)kernel; (void)model; (void)n_hint; (void)stream;
-  return fail(FV_E_UNSUPPORTED, "autotune not built yet");
+  if (kernel < 0 || kernel >= FV_KERNEL_COUNT) return fail(FV_E_INVALID_ARG, "kernel id");
+  if (model < FV_MODEL_BLACK76 || model > FV_MODEL_BSM)
+    return fail(FV_E_INVALID_ARG, "model out of range");
+  if (n_hint < 0) return fail(FV_E_INVALID_ARG, "n_hint < 0");
+  // time on a batch large enough to fill the device, at most n_hint quotes
+  int64_t n = std::max<int64_t>(std::min<int64_t>(n_hint, 1 << 24), 1 << 18);
+  const int per_mat = 256, mats = 8;
+  n = (n / (per_mat * mats)) * (per_mat * mats);
+  const int64_t n_mat = n / per_mat, n_chains = n_mat / mats;
+  hipStream_t s = (hipStream_t)stream;
+
+  // scratch for this call only
+  std::vector<void*> bufs;
+  auto alloc = [&](size_t bytes) -> void* {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    bufs.push_back(p);
+    return p;
+  };
+  auto release = [&]() {
+    for (void* p : bufs) hipFree(p);
+    bufs.clear();
+  };
+  double *S = (double*)alloc(n * 8), *K = (double*)alloc(n * 8), *T = (double*)alloc(n * 8),
+         *r = (double*)alloc(n * 8), *q = (double*)alloc(n * 8), *sig = (double*)alloc(n * 8),
+         *P = (double*)alloc(n * 8), *o1 = (double*)alloc(n * 8), *o2 = (double*)alloc(n * 8);
+  int8_t* flag = (int8_t*)alloc(n);
+  uint8_t* st = (uint8_t*)alloc(n);
+  int64_t *cmo = (int64_t*)alloc((n_chains + 1) * 8), *mqo = (int64_t*)alloc((n_mat + 1) * 8);
+  double *cF = (double*)alloc(n_chains * 8), *cr = (double*)alloc(n_chains * 8),
+         *cT = (double*)alloc(n_mat * 8);
+  for (void* p : bufs)
+    if (!p) {
+      release();
+      return fail(FV_E_HIP, "fv_autotune: device allocation failed");
+    }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    release();
+    return fail(FV_E_HIP, "fv_autotune: event creation failed");
+  }
+  const unsigned g256 = (unsigned)((n + 255) / 256);
+  k_tune_quotes<<<g256, 256, 0, s>>>(n, S, K, T, r, q, sig, flag);
+  k_tune_chains<<<(unsigned)((n_mat + 256) / 256), 256, 0, s>>>(n_chains, n_mat, n, mats, per_mat,
+                                                              T, r, cmo, mqo, cF, cr, cT);
+
+  fv_quotes qs;
+  memset(&qs, 0, sizeof(qs));
+  qs.n = n;
+  qs.price.ptr = P;
+  qs.fs.ptr = S;
+  qs.K.ptr = K;
+  qs.T.ptr = T;
+  qs.r.ptr = r;
+  qs.q.ptr = q;
+  qs.flag = flag;
+  fv_arg sa;
+  sa.ptr = sig;
+  sa.value = 0.0;
+  fv_chains cs;
+  memset(&cs, 0, sizeof(cs));
+  cs.n_chains = n_chains;
+  cs.n_maturities = n_mat;
+  cs.n_quotes = n;
+  cs.chain_mat_off = cmo;
+  cs.mat_quote_off = mqo;
+  cs.F = cF;
+  cs.r = cr;
+  cs.T = cT;
+  cs.price = P;
+  cs.K = K;
+  cs.flag = flag;
+
+  const LaunchShape saved_price = g_shape[FV_KERNEL_PRICE];
+  g_shape[FV_KERNEL_PRICE] = {256, 1};
+  int rc = FV_OK;
+  // input prices: the model's own prices of sigma (the chain kernel reads
+  // Black-76 prices of the chain forwards)
+  if (kernel == FV_KERNEL_CHAINS) {
+    k_tune_expand<<<g256, 256, 0, s>>>(n, mats, per_mat, cT, cr, o1, o2);
+    fv_quotes cq = qs;
+    cq.fs.ptr = nullptr;
+    cq.fs.value = 100.0;
+    cq.T.ptr = o1;
+    cq.r.ptr = o2;
+    rc = fv_price(FV_MODEL_BLACK76, &cq, sa, P, stream);
+  } else {
+    rc = fv_price(model, &qs, sa, P, stream);
+  }
+  g_shape[FV_KERNEL_PRICE] = saved_price;
+
+  auto run = [&]() -> int {
+    switch (kernel) {
+      case FV_KERNEL_PRICE: return fv_price(model, &qs, sa, o1, stream);
+      case FV_KERNEL_IV_LBR: return fv_implied_vol(model, FV_SOLVER_LBR, &qs, o1, st, nullptr, stream);
+      case FV_KERNEL_IV_HALLEY:
+        return fv_implied_vol(model, FV_SOLVER_HALLEY, &qs, o1, st, nullptr, stream);
+      case FV_KERNEL_GREEKS: return fv_greeks(model, &qs, sa, o1, o2, nullptr, nullptr, nullptr, stream);
+      case FV_KERNEL_BACKWARD:
+        return fv_implied_vol_backward(model, &qs, sig, sig, o1, o2, nullptr, nullptr, nullptr,
+                                       nullptr, stream);
+      default: return fv_implied_vol_chains(FV_SOLVER_LBR, &cs, o1, st, stream);
+    }
+  };
+  const int blocks[] = {64, 128, 256, 512};
+  const int qpts[] = {1, 2, 4};
+  LaunchShape best = g_shape[kernel];
+  float best_ms = 1e30f;
+  for (int b : blocks) {
+    for (int qq : qpts) {
+      if (rc != FV_OK) break;
+      g_shape[kernel] = {b, qq};
+      rc = run();  // warm-up
+      float tot = 0.0f, mn = 1e30f;
+      for (int rep = 0; rep < 3 && rc == FV_OK; ++rep) {
+        hipEventRecord(e0, s);
+        rc = run();
+        hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) rc = fail(FV_E_HIP, "fv_autotune: sync");
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        tot += ms;
+        mn = std::min(mn, ms);
+      }
+      (void)tot;
+      if (rc == FV_OK && mn < best_ms) {
+        best_ms = mn;
+        best = {b, qq};
+      }
+    }
+  }
+  g_shape[kernel] = best;
+  hipStreamSynchronize(s);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  release();
+  return rc;
 }
 
 }  // extern "C"

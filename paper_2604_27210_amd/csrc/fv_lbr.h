@@ -98,28 +98,33 @@ struct LbrResult {
 // lambda = b'/b (lower) or mu = b'/(b_max - b) (upper), eta = b''/b' and
 // eta3b = b'''/b'; step = nu (1 + eta2 nu/2) / (1 + nu (eta2 + eta3 nu/6)).
 __host__ __device__ inline double householder3_step(int obj, double x, double s, double beta,
-                                                     double ln_beta, double bmax,
+                                                     double inv_ln_beta, double bmax_m_beta,
                                                      const NBlack& nb) {
-  const double eta = nb_d2_over_d1(x, s);
-  const double eta3b = nb_d3_over_d1(x, s, eta);
+  const double is = 1.0 / s;
+  const double x2is2 = x * x * is * is;
+  const double eta = x2is2 * is - 0.25 * s;                       // b''/b'
+  const double eta3b = eta * eta - 3.0 * x2is2 * is * is - 0.25;  // b'''/b'
   double nu, e2, e3;
-  if (obj == kObjLower) {
-    const double L = log(nb.b);
-    const double lam = nb.bp / nb.b;
-    const double iL = 1.0 / L;
-    nu = L * (ln_beta - L) / (lam * ln_beta);
-    e2 = eta - lam * (1.0 + 2.0 * iL);
-    e3 = eta3b - 3.0 * lam * eta + 2.0 * lam * lam - 6.0 * lam * (eta - lam) * iL +
-         6.0 * lam * lam * iL * iL;
-  } else if (obj == kObjUpper) {
-    const double mu = nb.bp / nb.c;
-    nu = -log((bmax - beta) / nb.c) / mu;
-    e2 = eta + mu;
-    e3 = eta3b + 3.0 * mu * eta + 2.0 * mu * mu;
-  } else {
+  if (obj == kObjMiddle) {
     nu = (beta - nb.b) / nb.bp;
     e2 = eta;
     e3 = eta3b;
+  } else {
+    // lower and upper share one log and one division
+    const bool lo = obj == kObjLower;
+    const double w = nb.bp / (lo ? nb.b : nb.c);  // lambda = b'/b  or  mu = b'/(b_max - b)
+    const double L = log(lo ? nb.b : bmax_m_beta / nb.c);
+    const double iw = 1.0 / w;
+    if (lo) {
+      const double iL = 1.0 / L;
+      nu = L * (1.0 - L * inv_ln_beta) * iw;
+      e2 = eta - w * (1.0 + 2.0 * iL);
+      e3 = eta3b - 3.0 * w * eta + 2.0 * w * w - 6.0 * w * (eta - w) * iL + 6.0 * w * w * iL * iL;
+    } else {
+      nu = -L * iw;
+      e2 = eta + w;
+      e3 = eta3b + 3.0 * w * eta + 2.0 * w * w;
+    }
   }
   double ds = nu * (1.0 + 0.5 * e2 * nu) / (1.0 + nu * (e2 + e3 * nu * (1.0 / 6.0)));
   if (!(ds == ds)) ds = 0.0;
@@ -137,82 +142,106 @@ __host__ __device__ inline double householder3_step(int obj, double x, double s,
 //   R4  beta > b_u          rational cubic of the upper map f_u(s) = Phi(-s/2),
 //                           slope -1/2 at b_max, then s = -2 Phi^{-1}(f).
 // Returns s0 and sets the objective region of the iteration.
-__host__ __device__ inline double lbr_initial_guess(double x, double beta, double bmax,
-                                                    int* obj) {
+// `trace` (may be NULL) receives the path taken: bits 0-1 the guess region
+// (0..3 for R1..R4), bits 4-5 and 6-7 the evaluation forms at s_c and s_o.
+__host__ __device__ __attribute__((always_inline)) inline double lbr_initial_guess(
+    double x, double beta, double bmax, int* obj, uint32_t* trace) {
   const double ax = -x;  // |x|, x <= 0
   const double sc = sqrt(2.0 * ax);
   const NBlack nc = normalised_black(x, sc, bmax);
   const bool lower_half = beta < nc.b;
   // the other boundary point on the side of beta
-  const double so = lower_half ? fmax(sc - nc.b / nc.bp, 0.0) : sc + nc.c / nc.bp;
+  const double ibc = 1.0 / nc.bp;
+  const double so = lower_half ? fmax(sc - nc.b * ibc, 0.0) : sc + nc.c * ibc;
   const NBlack no = normalised_black(x, so, bmax);
+  const double ibo = 1.0 / no.bp;
 
   const bool r1 = lower_half && beta < no.b;
   const bool r4 = !lower_half && beta > no.b;
+  const bool wing = r1 || r4;
   *obj = r1 ? kObjLower : (r4 ? kObjUpper : kObjMiddle);
+  if (trace)
+    *trace = (uint32_t)(r1 ? 0 : (lower_half ? 1 : (r4 ? 3 : 2))) | ((uint32_t)nc.form << 4) |
+             ((uint32_t)no.form << 6);
 
-  if (!(r1 || r4)) {
-    // R2 / R3: interpolate s(beta) between the two boundary points; slopes
-    // ds/dbeta = 1/b'.  b'' = 0 at s_c gives zero curvature at b_c.
-    if (lower_half)
-      return rational_cubic_fit(beta, no.b, nc.b, so, sc, 1.0 / no.bp, 1.0 / nc.bp, 0.0,
-                                false);
-    return rational_cubic_fit(beta, nc.b, no.b, sc, so, 1.0 / nc.bp, 1.0 / no.bp, 0.0, true);
-  }
-
-  // R1 / R4: one Phi evaluation at the transformed boundary point.
-  //   f(beta) derivatives from the chain rule with b' and
-  //   b''/b' = eta:  df/dbeta = f'/b',  d2f/dbeta2 = (f'' - f' eta)/b'^2.
-  const double eta_o = nb_d2_over_d1(x, so);
-  double guess;
-  if (r1) {
-    const double cl = 2.0 * kPi * ax / (3.0 * kSqrt3);
-    const double z = -ax / (kSqrt3 * so);
-    const double Pz = norm_cdf(z), pz = norm_pdf(z);
-    const double zp = -z / so;               // dz/ds
-    const double fl = cl * Pz * Pz * Pz;
-    const double f1 = 3.0 * cl * Pz * Pz * pz * zp;
-    const double f2 = 3.0 * cl * (2.0 * Pz * pz * pz * zp * zp - Pz * Pz * z * pz * zp * zp +
-                                  Pz * Pz * pz * (-2.0 * zp / so));
-    const double dr = f1 / no.bp;
-    const double c2 = (f2 - f1 * eta_o) / (no.bp * no.bp);
-    double f = rational_cubic_fit(beta, 0.0, no.b, 0.0, fl, 1.0, dr, c2, false);
-    f = fmax(f, 1e-300);
-    const double u = cbrt(f / cl);           // Phi(z) at the guess, < 1/2
-    guess = -ax / (kSqrt3 * inv_norm_cdf_lower(fmin(u, 0.4999999999)));
+  // End data of the one rational cubic every lane evaluates.
+  // R2: s(beta) on [b_l, b_c], slopes 1/b', zero curvature at b_c (b'' = 0
+  //     at the inflection point): fit at the right end.
+  // R3: s(beta) on [b_c, b_u], same, fit at the left end.
+  double xl, xr, yl, yr, dl, dr, c2 = 0.0;
+  bool fit_left = !lower_half;
+  if (lower_half) {
+    xl = no.b; xr = nc.b; yl = so; yr = sc; dl = ibo; dr = ibc;
   } else {
-    const double z = -0.5 * so;
-    const double fu = norm_cdf(z), pz = norm_pdf(z);
-    const double f1 = -0.5 * pz;             // d f_u / ds
-    const double f2 = 0.125 * so * pz;       // d2 f_u / ds2
-    const double dl = f1 / no.bp;
-    const double c2 = (f2 - f1 * eta_o) / (no.bp * no.bp);
-    double f = rational_cubic_fit(beta, no.b, bmax, fu, 0.0, dl, -0.5, c2, true);
-    f = fmin(fmax(f, 1e-300), 0.5);
-    guess = -2.0 * inv_norm_cdf_lower(f);
+    xl = nc.b; xr = no.b; yl = sc; yr = so; dl = ibc; dr = ibo;
   }
-  return guess;
+  const double cl = 2.0 * kPi * ax / (3.0 * kSqrt3);
+  if (wing) {
+    // R1 / R4 share one Phi/phi evaluation at the transformed boundary point
+    // (lower map: z = -|x|/(sqrt3 s_l); upper map: z = -s_u/2).  With
+    // b''/b' = eta:  df/dbeta = f'/b',  d2f/dbeta2 = (f'' - f' eta)/b'^2.
+    const double eta_o = nb_d2_over_d1(x, so);
+    const double z = r1 ? -ax / (kSqrt3 * so) : -0.5 * so;
+    const double ez = exp(-0.5 * z * z);
+    const double Pz = 0.5 * ez * erfcx_nonneg(-z * kInvSqrt2);  // Phi(z), z <= 0
+    const double pz = kInvSqrt2Pi * ez;                          // phi(z)
+    double f0, f1, f2;  // f, df/ds, d2f/ds2 at s_o
+    if (r1) {
+      const double zp = -z / so;  // dz/ds
+      f0 = cl * Pz * Pz * Pz;
+      f1 = 3.0 * cl * Pz * Pz * pz * zp;
+      f2 = 3.0 * cl * zp * zp * Pz * pz * (2.0 * pz - Pz * z - 2.0 * Pz / (so * zp));
+    } else {
+      f0 = Pz;
+      f1 = -0.5 * pz;
+      f2 = 0.125 * so * pz;
+    }
+    const double dfo = f1 * ibo;
+    const double c2o = (f2 - f1 * eta_o) * ibo * ibo;
+    if (r1) {
+      // f on [0, b_l]: (0, 0) slope 1 -> (b_l, f_l(s_l)) slope dfo; fit right
+      xl = 0.0; xr = no.b; yl = 0.0; yr = f0; dl = 1.0; dr = dfo; c2 = c2o; fit_left = false;
+    } else {
+      // f on [b_u, b_max]: (b_u, f_u(s_u)) slope dfo, fit left -> (b_max, 0) slope -1/2
+      xl = no.b; xr = bmax; yl = f0; yr = 0.0; dl = dfo; dr = -0.5; c2 = c2o; fit_left = true;
+    }
+  }
+  const double y = rational_cubic_fit(beta, xl, xr, yl, yr, dl, dr, c2, fit_left);
+  if (!wing) return y;
+  // invert the map: R1 Phi(z) = (f/cl)^{1/3}, s = -|x|/(sqrt3 z);
+  //                 R4 Phi(-s/2) = f,          s = -2 z.
+  const double f = fmax(y, 1e-300);
+  const double p = r1 ? fmin(cbrt(f / cl), 0.4999999999) : fmin(f, 0.5);
+  const double zi = inv_norm_cdf_lower(p);
+  return r1 ? -ax / (kSqrt3 * zi) : -2.0 * zi;
 }
 
 // Full LBR solve: guess, then Householder(3) steps.  `min_steps` steps are
 // always taken; more (up to `max_steps`) while the last step exceeds
 // `step_tol` relative -- on the GPU this makes the extra step a wave-level
 // decision, taken only by waves holding a lane that needs it.
-__host__ __device__ inline LbrResult lbr_solve(double x, double beta, int min_steps,
-                                               int max_steps, double step_tol) {
+// `trace` (may be NULL) receives the guess path (see lbr_initial_guess),
+// bits 2-3 the number of steps minus 2 and, from bit 8, two bits per step
+// for the evaluation form of that step.
+__host__ __device__ __attribute__((always_inline)) inline LbrResult lbr_solve(
+    double x, double beta, int min_steps, int max_steps, double step_tol,
+    uint32_t* trace = nullptr) {
   const double bmax = exp(0.5 * x);
   int obj;
-  double s = lbr_initial_guess(x, beta, bmax, &obj);
-  const double ln_beta = log(beta);
+  double s = lbr_initial_guess(x, beta, bmax, &obj, trace);
+  const double inv_ln_beta = 1.0 / log(beta);
+  const double bmax_m_beta = bmax - beta;
   LbrResult res;
   int it = 0;
   double ds = 0.0;
   for (; it < max_steps; ++it) {
     if (it >= min_steps && !(fabs(ds) > step_tol * s)) break;
     const NBlack nb = normalised_black(x, s, bmax);
-    ds = householder3_step(obj, x, s, beta, ln_beta, bmax, nb);
+    if (trace) *trace |= (uint32_t)nb.form << (8 + 2 * it);
+    ds = householder3_step(obj, x, s, beta, inv_ln_beta, bmax_m_beta, nb);
     s += ds;
   }
+  if (trace) *trace |= (uint32_t)(it - 2) << 2;
   res.s = s;
   res.iterations = it;
   res.converged = !(fabs(ds) > step_tol * s) || it < max_steps;
@@ -231,7 +260,7 @@ struct HalleyState {
 // A bracket [lo, hi] from the sign of the residual keeps every iterate
 // inside; a step that would leave it bisects instead (geometrically).
 // Converged: last |step| <= 1e-10 s and |b - beta| <= 1e-9 beta.
-__host__ __device__ inline HalleyState halley_solve(double x, double beta, int steps) {
+__host__ __device__ __attribute__((always_inline)) inline HalleyState halley_solve(double x, double beta, int steps) {
   const double bmax = exp(0.5 * x);
   HalleyState st;
   st.lo = 0.0;

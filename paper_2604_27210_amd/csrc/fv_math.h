@@ -36,11 +36,27 @@ constexpr double kEps = 2.220446049250313e-16;
 constexpr double kTauSmall = 0.21022410381342863;
 constexpr double kHLarge = -10.0;
 
+// ----------------------------------------------------------- reciprocal
+// 1/x for finite normal x: the hardware estimate v_rcp_f64 refined by two
+// Newton steps (r <- r + r (1 - x r)), within ~1 ulp.  Cheaper than an IEEE
+// division, which also handles denormal and overflowing operands that these
+// call sites never produce.
+__host__ __device__ inline double rcp(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+#else
+  return 1.0 / x;
+#endif
+}
+
 // ----------------------------------------------------------------- erfcx
 // erfcx(z) = exp(z^2) erfc(z) for z >= 0, one branch-free polynomial in
 // y = (z - K)/(z + K) (fitted coefficients, fv_coeffs.h).
 __host__ __device__ inline double erfcx_nonneg(double z) {
-  const double R = 1.0 / (z + coef::kErfcxK);
+  const double R = rcp(z + coef::kErfcxK);
   const double y = (z - coef::kErfcxK) * R;
   double p = coef::kErfcx[23];
 #pragma unroll
@@ -109,11 +125,13 @@ struct NBlack {
   double b;   // b(x, s)
   double c;   // b_max - b(x, s)
   double bp;  // db/ds
+  int form;   // evaluation form taken (kFormAsymptotic ... kFormComplement)
 };
 
-__host__ __device__ inline double nb_small_t_ratio(double h, double t) {
-  // Y(h) for h <= 0
-  const double y0 = kSqrtPiOver2 * erfcx_nonneg(-h * kInvSqrt2);
+enum NbForm : int { kFormAsymptotic = 0, kFormSmallT = 1, kFormErfcx = 2, kFormComplement = 3 };
+
+// y0 = Y(h) = sqrt(pi/2) erfcx(-h/sqrt2) for h <= 0.
+__host__ __device__ inline double nb_small_t_ratio(double h, double t, double y0) {
   double ym = y0;                 // Y^{(k-1)}
   double yk = fma(h, y0, 1.0);    // Y^{(1)}
   const double t2 = t * t;
@@ -127,7 +145,7 @@ __host__ __device__ inline double nb_small_t_ratio(double h, double t) {
     const double y2 = fma(h, y1, (k + 1) * yk);
     ym = y1;
     yk = y2;
-    tp *= t2 / ((k + 1) * (k + 2));
+    tp *= t2 * (1.0 / ((k + 1) * (k + 2)));
     sum = fma(tp, yk, sum);
   }
   return 2.0 * t * sum;
@@ -148,33 +166,44 @@ __host__ __device__ inline double nb_asymptotic_ratio(double h, double t) {
   return 2.0 * t / (A * B) * sum;
 }
 
-// x <= 0, s >= 0, bmax = exp(x/2).
+// x <= 0, s >= 0, bmax = exp(x/2).  The small-t and erfcx forms share their
+// first erfcx call (argument -h/sqrt2 or |q1|), so a wave mixing the two
+// forms evaluates two erfcx, not three.
 __host__ __device__ inline NBlack normalised_black(double x, double s, double bmax) {
   NBlack r;
+  r.form = kFormErfcx;
   if (!(s > 0.0)) {
     r.b = 0.0;
     r.c = bmax;
     r.bp = (x == 0.0) ? kInvSqrt2Pi : 0.0;
     return r;
   }
-  const double h = x / s, t = 0.5 * s;
+  const double h = x * rcp(s), t = 0.5 * s;
   const double E = exp(-0.5 * fma(h, h, t * t));
   r.bp = kInvSqrt2Pi * E;
-  if (h < kHLarge && h + t < kHLarge + kTauSmall) {
+  const bool asym = h < kHLarge && h + t < kHLarge + kTauSmall;
+  if (asym) {
     r.b = r.bp * nb_asymptotic_ratio(h, t);
     r.c = bmax - r.b;
-  } else if (t < kTauSmall) {
-    r.b = r.bp * nb_small_t_ratio(h, t);
+    r.form = kFormAsymptotic;
+    return r;
+  }
+  const bool small = t < kTauSmall;
+  const double q1 = -(h + t) * kInvSqrt2;
+  const double e1 = erfcx_nonneg(small ? -h * kInvSqrt2 : fabs(q1));
+  if (small) {
+    r.b = r.bp * nb_small_t_ratio(h, t, kSqrtPiOver2 * e1);
     r.c = bmax - r.b;
+    r.form = kFormSmallT;
   } else {
-    const double q1 = -(h + t) * kInvSqrt2, q2 = (t - h) * kInvSqrt2;
-    const double e1 = erfcx_nonneg(fabs(q1)), e2 = erfcx_nonneg(q2);
+    const double e2 = erfcx_nonneg((t - h) * kInvSqrt2);
     if (q1 >= 0.0) {
       r.b = 0.5 * E * (e1 - e2);
       r.c = bmax - r.b;
     } else {
       r.c = 0.5 * E * (e1 + e2);
       r.b = bmax - r.c;
+      r.form = kFormComplement;
     }
   }
   return r;

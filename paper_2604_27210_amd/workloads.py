@@ -185,3 +185,31 @@ def b76_chains(n_chains: int = 2000, seed: int = 3) -> Chains:
     sig = 0.2 + 0.1 * k * k - 0.05 * k
     flag = np.where(K < F[chain], -1, 1).astype(np.int8)
     return Chains(chain_mat_off, mat_quote_off, F, r, T, K, flag, sig, k)
+
+
+@dataclass
+class SviCalibration:
+    """Calibration workload: ragged Black-76 chains plus per-maturity SVI
+    parameters in natural units (a, b, rho, m, s) -- the generating set
+    ``theta_true`` and a perturbed starting point ``theta0`` -- and the
+    relative noise ``eps`` that perturbs each target volatility."""
+    chains: Chains
+    theta_true: np.ndarray   # [n_mat, 5]
+    theta0: np.ndarray       # [n_mat, 5]
+    eps: np.ndarray          # [n_quotes]
+
+
+SVI_RANGES = np.array([[0.005, 0.03], [0.05, 0.3], [-0.7, 0.0], [-0.1, 0.1], [0.05, 0.3]])
+
+
+def svi_calibration(n_chains: int = 500, seed: int = 5) -> SviCalibration:
+    """Chains as ``b76_chains``; per maturity a~U[0.005,0.03], b~U[0.05,0.3],
+    rho~U[-0.7,0], m~U[-0.1,0.1], s~U[0.05,0.3]; start = truth + N(0, (20% of
+    each range)^2), clipped into the range; eps~N(0, 0.01^2) per quote."""
+    ch = b76_chains(n_chains, seed=seed)
+    rng = np.random.default_rng(seed + 100)
+    lo, hi = SVI_RANGES[:, 0], SVI_RANGES[:, 1]
+    th = lo + (hi - lo) * rng.random((ch.n_mat, 5))
+    th0 = np.clip(th + rng.standard_normal((ch.n_mat, 5)) * 0.2 * (hi - lo), lo, hi)
+    eps = rng.normal(0.0, 0.01, ch.n)
+    return SviCalibration(ch, th, th0, eps)

@@ -7,7 +7,7 @@ import pytest
 import oracle
 from paper_2604_27210_amd import workloads as W
 
-from _helpers import assemble_prices
+from _helpers import U, assemble_prices, cond_abs
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -66,16 +66,23 @@ def test_iv_autograd_central_differences(fv):
     sig, st = fv.implied_vol_autograd("bsm", *ins[:5], flag=fl, q=ins[5])
     sig.sum().backward()
     ok = st.cpu().numpy() == 0
+    # rounding noise of a binary64 IV evaluation (a few ulps of the summed
+    # input sensitivities), which a difference quotient divides by 2h
+    noise = 8 * U * cond_abs("bsm", P, wl.fs, wl.K, wl.T, wl.r, wl.q, wl.flag)
     for j, k in enumerate(("price", "fs", "K", "T", "r", "q")):
         x = base[k]
         h = 1e-6 * (np.abs(x) if k in ("price", "fs", "K", "T") else np.ones_like(x))
         fd = (iv(**{k: x + h}) - iv(**{k: x - h})) / (2 * h)
         g = ins[j].grad.cpu().numpy()
-        rel = np.abs(g - fd) / np.maximum(np.abs(g), 1e-12)
         # a shifted input can leave the solvable domain (price above its bound)
         m = ok & np.isfinite(fd)
         assert m.mean() > 0.99
-        assert np.median(rel[m]) < 1e-8 and np.quantile(rel[m], 0.99) < 1e-5, (k, rel[m].max())
+        # truncation O(h^2) relative plus the rounding noise of the two solves
+        bound = 1e-6 * np.abs(g) + noise / h + 1e-12
+        bad = m & ~(np.abs(g - fd) <= bound)
+        assert bad.sum() == 0, (k, np.where(bad)[0][:5])
+        rel = np.abs(g - fd) / np.maximum(np.abs(g), 1e-12)
+        assert np.median(rel[m]) < 1e-8, k
 
 
 def test_composite_identity(fv):

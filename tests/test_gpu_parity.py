@@ -309,3 +309,21 @@ def test_invalid_calls_raise(fv):
         fv.implied_vol("bsm", d, d, d, d, d, solver=5)
     with pytest.raises((ValueError, TypeError)):
         fv.implied_vol("bsm", d, d, d.float(), d, d)
+
+
+def test_autotune_picks_a_valid_shape_and_results_do_not_change(fv):
+    wl = W.bsm_wide(50_000, seed=21, inject=0.0)
+    P = assemble_prices(wl)
+    s_ref, st_ref = run_iv(fv, wl, P, "lbr")
+    try:
+        b, q = fv.autotune("iv_lbr", "bsm", 1 << 20)
+        assert b % 64 == 0 and 64 <= b <= 512 and 1 <= q <= 16
+        s, st = run_iv(fv, wl, P, "lbr")
+        assert torch.equal(torch.nan_to_num(s, nan=-1.0), torch.nan_to_num(s_ref, nan=-1.0))
+        assert torch.equal(st, st_ref)
+        for kern in ("price", "iv_halley", "greeks", "backward", "chains"):
+            b, q = fv.autotune(kern, "black76" if kern == "chains" else "bsm", 1 << 19)
+            assert b % 64 == 0 and 1 <= q <= 16
+    finally:
+        for kern in ("price", "iv_lbr", "iv_halley", "greeks", "backward", "chains"):
+            fv.set_launch(kern, 256, 1)
