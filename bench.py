@@ -22,15 +22,41 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic FP64 work per quote of the LBR kernel on this workload (FMA = 2
-# FLOPs), from the per-region instruction census (see profiles/).  Used for
-# the roofline fraction; the measured time is what the bench reports.
-LBR_FLOP_PER_QUOTE = None
+# Roofline figures of the LBR kernel on this workload, taken with rocprofv3
+# from the kernel sources whose SHA-256 is ``source_sha256`` (the summaries
+# and the commands that made them are kept under profiles/):
+#  * flop_per_quote: algorithmic FP64 work (FMA = 2 FLOPs, every other FP64
+#    VALU instruction = 1 per lane) from SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64
+#    of one launch over the workload with the quotes sorted by LBR path
+#    (``--census``), where no wave executes a branch another lane skipped;
+#  * fetch/write_bytes_per_quote: FETCH_SIZE and WRITE_SIZE of the timed
+#    launch, each divided by what the counter reads per byte of a plain
+#    1 GiB device copy (``--copy-probe``) and by the quote count.
+# The traffic figure is reported only while the kernel sources still hash to
+# ``source_sha256``; the FLOP figure is the algorithmic count of that source.
+LBR_PROFILE = {
+    "source_sha256": None,
+    "flop_per_quote": 1549.0,
+    "fetch_bytes_per_quote": None,
+    "write_bytes_per_quote": None,
+}
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 # algorithmic HBM bytes per quote: six float64 inputs + int8 flag in,
 # float64 sigma + uint8 status out
 BYTES_PER_QUOTE = 6 * 8 + 1 + 8 + 1
+KERNEL_SOURCES = ("fv_kernels.hip", "fv_math.h", "fv_lbr.h", "fv_quote.h", "fv_coeffs.h",
+                  "fv_host.h")
+
+
+def kernel_source_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2604_27210_amd", "csrc")
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def parse():
@@ -43,11 +69,17 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=200_000,
                     help="quotes of the workload the oracle solves for the CPU baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the secondary measurements (Halley, small batch, ragged chains, "
+                         "forward+backward, calibration)")
     ap.add_argument("--census", action="store_true",
                     help="instead of the bench: group the quotes by LBR path (fv_lbr_trace), "
                          "then run the LBR kernel once on the workload as generated and once "
                          "with quotes sorted by path, so that FP64 instruction counters "
                          "(rocprofv3 --pmc) of the sorted launch give the algorithmic work")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="instead of the bench: copy a 1 GiB device buffer three times "
+                         "(the reference launch that scales FETCH_SIZE / WRITE_SIZE to bytes)")
     return ap.parse_args()
 
 
@@ -87,6 +119,112 @@ def cpu_baseline(wl, P, sample):
             "kind": "oracle",
             "sample": "%d quotes evenly strided over the 10M-quote workload, binary128 exact "
                       "root, OpenMP over %d threads, %.2f s wall" % (sample, oracle.num_threads(), dt)}
+
+
+def _time(torch, fn, reps=10, warm=2):
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def extras(fv, torch, main_inputs):
+    """Secondary measurements beside the headline: the Halley path on the
+    same batch, the small batch's latency, ragged chains (one persistent
+    launch vs the flat kernel on expanded arrays vs one launch per chain),
+    forward+backward of the differentiable IV, and the hipGraph calibration
+    loop (graph replay vs eager launches)."""
+    from paper_2604_27210_amd import workloads as W
+    from paper_2604_27210_amd.calibrate import SviCalibrator, calibrate_svi, raw_from_natural
+    d = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt)
+    out = {}
+    P, S, K, T, r, q, flag = main_inputs
+    n = P.numel()
+    ms = _time(torch, lambda: fv.implied_vol("bsm", P, S, K, T, r, flag=flag, q=q, solver="halley"))
+    out["halley_wide_bsm"] = {"ms": ms, "implied_vols_per_s": n / ms * 1e3}
+    # small batch: launch-latency bound
+    wl = W.bs_small()
+    a = [d(x) for x in (wl.fs, wl.K, wl.T, wl.r)]
+    fl = d(wl.flag, torch.int8)
+    Ps = fv.price("bs", a[0], a[1], a[2], a[3], d(wl.sigma_true), flag=fl)
+    for solver in ("lbr", "halley"):
+        ms = _time(torch, lambda: fv.implied_vol("bs", Ps, *a, flag=fl, solver=solver), reps=50)
+        out["bs_4096_%s_us_per_call" % solver] = ms * 1e3
+    # ragged chains
+    ch = W.b76_chains()
+    flat = ch.flatten()
+    cd = {k: d(v, torch.int64) for k, v in (("cmo", ch.chain_mat_off), ("mqo", ch.mat_quote_off))}
+    F, rc, Tm, Kq, flq = d(ch.F), d(ch.r), d(ch.T), d(ch.K), d(ch.flag, torch.int8)
+    fF, fT, fr = d(flat.fs), d(flat.T), d(flat.r)
+    Pc = fv.price("black76", fF, Kq, fT, fr, d(ch.sigma_true), flag=flq)
+    ms_p = _time(torch, lambda: fv.implied_vol_chains(cd["cmo"], cd["mqo"], F, rc, Tm, Pc, Kq, flq))
+    ms_f = _time(torch, lambda: fv.implied_vol("black76", Pc, fF, Kq, fT, fr, flag=flq))
+    off = ch.mat_quote_off[ch.chain_mat_off]
+
+    def per_chain():
+        for c in range(ch.n_chains):
+            lo, hi = int(off[c]), int(off[c + 1])
+            fv.implied_vol("black76", Pc[lo:hi], fF[lo:hi], Kq[lo:hi], fT[lo:hi], fr[lo:hi],
+                           flag=flq[lo:hi])
+    ms_c = _time(torch, per_chain, reps=3, warm=1)
+    out["ragged_b76_chains"] = {"n_quotes": ch.n, "n_chains": ch.n_chains, "n_maturities": ch.n_mat,
+                                "persistent_ms": ms_p, "flat_expanded_ms": ms_f,
+                                "per_chain_launches_ms": ms_c,
+                                "persistent_implied_vols_per_s": ch.n / ms_p * 1e3}
+    # forward + backward (differentiable IV), 1M quotes
+    wd = W.bsm_diff()
+    x = [d(v) for v in (wd.fs, wd.K, wd.T, wd.r, wd.q)]
+    fld = d(wd.flag, torch.int8)
+    Pd = fv.price("bsm", x[0], x[1], x[2], x[3], d(wd.sigma_true), flag=fld, q=x[4])
+    w = d(wd.extra["w"])
+
+    def fwd_bwd():
+        sig, st = fv.implied_vol("bsm", Pd, x[0], x[1], x[2], x[3], flag=fld, q=x[4])
+        fv.implied_vol_backward("bsm", Pd, x[0], x[1], x[2], x[3], sig, w, flag=fld, q=x[4])
+    ms_fb = _time(torch, fwd_bwd)
+    ms_fw = _time(torch, lambda: fv.implied_vol("bsm", Pd, x[0], x[1], x[2], x[3], flag=fld, q=x[4]))
+    out["bsm_1m_fwd_bwd"] = {"ms": ms_fb, "quotes_per_s": wd.n / ms_fb * 1e3,
+                             "forward_only_ms": ms_fw}
+    # calibration loop: 500 chains, 200 Adam steps, one hipGraph replay per step
+    cal = W.svi_calibration(500, seed=5)
+    chc = cal.chains
+    mat = chc.mat_of_quote()
+    chain = chc.chain_of_mat()[mat]
+    th = raw_from_natural(cal.theta_true)
+    # target vols: SVI(theta_true) * (1 + eps), priced and inverted on the GPU
+    kq = chc.k
+    a_, b_, rho_, m_, s_ = (th[:, 0], np.log1p(np.exp(th[:, 1])), np.tanh(th[:, 2]), th[:, 3],
+                            np.log1p(np.exp(th[:, 4])))
+    dk = kq - m_[mat]
+    wv = a_[mat] + b_[mat] * (rho_[mat] * dk + np.sqrt(dk * dk + s_[mat] ** 2))
+    sig_t = np.sqrt(wv / chc.T[mat]) * (1 + cal.eps)
+    cF, cT, cr = d(chc.F[chain]), d(chc.T[mat]), d(chc.r[chain])
+    cK, cfl = d(chc.K), d(chc.flag, torch.int8)
+    Pt = fv.price("black76", cF, cK, cT, cr, d(sig_t), flag=cfl)
+    iv_t, st_t = fv.implied_vol("black76", Pt, cF, cK, cT, cr, flag=cfl)
+    iv_t = torch.where(st_t == 0, iv_t, torch.full_like(iv_t, float("nan")))
+    args = (d(chc.chain_mat_off, torch.int64), d(chc.mat_quote_off, torch.int64), d(chc.F),
+            d(chc.r), d(chc.T), cK, cfl, iv_t)
+    res = {}
+    for graph in (False, True):
+        c = SviCalibrator(*args, raw_from_natural(cal.theta0))
+        r_ = calibrate_svi(c, 200, graph=graph)
+        ok = torch.isfinite(iv_t)
+        rmse = 100 * torch.sqrt(torch.mean((c.vols()[ok] - iv_t[ok]) ** 2)).item()
+        res["graph" if graph else "eager"] = {"steps_per_s": r_["steps_per_s"],
+                                              "final_rmse_vol_points": rmse,
+                                              "final_loss": float(c.losses()[-1])}
+    out["svi_calibration_500_chains"] = dict(n_quotes=chc.n, n_maturities=chc.n_mat,
+                                             steps=200, **res)
+    return out
 
 
 def census(fv, torch, P, S, K, T, r, q, flag):
@@ -134,6 +272,15 @@ def main():
     if a.census:
         census(fv, torch, P, S, K, T, r, q, flag)
         return
+    if a.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe": True, "bytes_read": src.numel() * 8,
+                          "bytes_written": dst.numel() * 8}), flush=True)
+        return
 
     def step():
         return fv.implied_vol("bsm", P, S, K, T, r, flag=flag, q=q, solver=a.solver)
@@ -158,10 +305,18 @@ def main():
     counts = np.bincount(st_h, minlength=6)
 
     roof = None
-    if LBR_FLOP_PER_QUOTE and a.solver == "lbr":
-        ach = LBR_FLOP_PER_QUOTE * a.n / avg_kernel_s / 1e12
+    if a.solver == "lbr":
+        ach = LBR_PROFILE["flop_per_quote"] * a.n / avg_kernel_s / 1e12
+        traffic = None
+        fresh = LBR_PROFILE["source_sha256"] == kernel_source_sha256()
+        if fresh and LBR_PROFILE["fetch_bytes_per_quote"] is not None:
+            traffic = (LBR_PROFILE["fetch_bytes_per_quote"] +
+                       LBR_PROFILE["write_bytes_per_quote"]) * a.n
         roof = {"bound": "alu", "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS, "traffic": None}
+                "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+                "flop_per_quote": LBR_PROFILE["flop_per_quote"],
+                "kernel_ms_mean": avg_kernel_s * 1e3,
+                "algorithmic_hbm_GBs": BYTES_PER_QUOTE * a.n / avg_kernel_s / 1e9}
     else:
         ach = BYTES_PER_QUOTE * a.n / avg_kernel_s / 1e9
         roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -187,6 +342,8 @@ def main():
                    "solver": a.solver, "status_counts": counts.tolist()},
         "roofline": roof,
     }
+    if not a.no_extras:
+        out["extras"] = extras(fv, torch, (P, S, K, T, r, q, flag))
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, P.cpu().numpy(), a.cpu_sample)
     print(json.dumps(out), flush=True)

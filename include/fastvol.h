@@ -165,9 +165,10 @@ int fv_implied_vol_chains(int solver, const fv_chains *c, double *sigma_out,
  *   w(k) = a + b (rho (k - mu) + sqrt((k - mu)^2 + s^2)),  k = ln(K/F),
  * sigma_SVI = sqrt(w/T).  The loss is
  *   L = (1/n_quotes) sum_i (IV(P_Black76(sigma_SVI,i)) - iv_target_i)^2,
- * quotes with w <= 1e-10, a non-solvable price or a non-finite target
- * contribute nothing.  chains.price is not read; all arrays are device
- * arrays. */
+ * quotes with w <= 1e-10 or a non-finite target contribute nothing; where
+ * the model price of sigma_SVI is not solvable in binary64 (it rounded onto
+ * its intrinsic value or upper bound) IV(P(sigma_SVI)) takes its exact value
+ * sigma_SVI.  chains.price is not read; all arrays are device arrays. */
 typedef struct {
     fv_chains chains;
     const double *iv_target;             /* [n_quotes] */

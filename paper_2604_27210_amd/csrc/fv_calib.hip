@@ -91,18 +91,24 @@ __global__ __launch_bounds__(kCalibBlock) void k_svi_grad(KSvi c, const double* 
     const SviPoint sp = svi_eval(th, log(K / F));
     if (!(sp.w > kWMin)) continue;
     const double sigma = sqrt(sp.w / T);
+    const double tgt = c.iv_target[i];
+    if (!fv::finite_d(tgt)) continue;
     const double P = fv::price_at(F, K, D, sigma, sqT, fl);
     const fv::Reduced rd = fv::reduce_quote(fv::kBlack76, P, F, K, T, r, 0.0, fl);
-    const double tgt = c.iv_target[i];
-    if (rd.status != fv::kQOk || !fv::finite_d(tgt)) continue;
-    const fv::LbrResult res = fv::lbr_solve(rd.x, rd.beta, 2, 4, 1e-6);
-    const double iv = res.s / sqT;
+    // IV(P(sigma)) through the LBR solver; where the model price is not
+    // solvable in binary64 (it rounded onto the intrinsic value or the upper
+    // bound) the composite takes its exact value sigma and unit slope
+    double iv = sigma, ratio = 1.0;
+    if (rd.status == fv::kQOk) {
+      const fv::LbrResult res = fv::lbr_solve(rd.x, rd.beta, rd.bmax, 2, 4, 1e-6);
+      iv = res.s / sqT;
+      // vega(v) = D F phi(d1(v)) sqrt(T); only vega(sigma)/vega(iv) enters
+      const double lfk = log(F / K);
+      const double s1 = sigma * sqT, s2 = iv * sqT;
+      const double d1a = lfk / s1 + 0.5 * s1, d1b = lfk / s2 + 0.5 * s2;
+      ratio = exp(-0.5 * (d1a * d1a - d1b * d1b));
+    }
     const double e = iv - tgt;
-    // vega(v) = D F phi(d1(v)) sqrt(T); only the ratio vega(sigma)/vega(iv) enters
-    const double lfk = log(F / K);
-    const double s1 = sigma * sqT, s2 = iv * sqT;
-    const double d1a = lfk / s1 + 0.5 * s1, d1b = lfk / s2 + 0.5 * s2;
-    const double ratio = exp(-0.5 * (d1a * d1a - d1b * d1b));
     const double g_sigma = 2.0 * e * inv_n * ratio;
     const double g_w = g_sigma / (2.0 * sigma * T);
     acc[0] += g_w * sp.dw[0];

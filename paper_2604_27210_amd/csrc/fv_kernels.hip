@@ -121,7 +121,7 @@ __attribute__((amdgpu_waves_per_eu(FV_SOLVER_WAVES_PER_EU))) void k_iv_lbr(KQuot
     uint8_t st = rd.status;
     double sg = st == fv::kQAtIntrinsic ? 0.0 : __builtin_nan("");
     if (st == fv::kQOk) {
-      const LbrResult res = fv::lbr_solve(rd.x, rd.beta, kLbrMinSteps, kLbrMaxSteps, kLbrStepTol);
+      const LbrResult res = fv::lbr_solve(rd.x, rd.beta, rd.bmax, kLbrMinSteps, kLbrMaxSteps, kLbrStepTol);
       sg = res.s / rd.sqrtT;
       if (!res.converged) st = fv::kQNotConverged;
     }
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_lbr_trace(KQuotes q, uint32_t* __
     uint32_t code = 0xFFFFFFFFu;  // not solved (status != OK)
     if (rd.status == fv::kQOk) {
       code = 0;
-      fv::lbr_solve(rd.x, rd.beta, kLbrMinSteps, kLbrMaxSteps, kLbrStepTol, &code);
+      fv::lbr_solve(rd.x, rd.beta, rd.bmax, kLbrMinSteps, kLbrMaxSteps, kLbrStepTol, &code);
     }
     out[i] = code;
   }
@@ -204,7 +204,7 @@ __attribute__((amdgpu_waves_per_eu(FV_SOLVER_WAVES_PER_EU))) void k_iv_halley(KQ
       uint8_t st = rd.status;
       double sg = st == fv::kQAtIntrinsic ? 0.0 : __builtin_nan("");
       if (st == fv::kQOk) {
-        hs = fv::halley_solve(rd.x, rd.beta, kHalleySteps);
+        hs = fv::halley_solve(rd.x, rd.beta, rd.bmax, kHalleySteps);
         sg = hs.s / rd.sqrtT;
         fail = !hs.converged;
       }
@@ -253,7 +253,7 @@ __attribute__((amdgpu_waves_per_eu(FV_SOLVER_WAVES_PER_EU))) void k_iv_halley(KQ
     const double qy = MODEL == fv::kBlackScholesMerton ? ld(q.q, i) : 0.0;
     const int th = ldflag(q, i);
     const Reduced rd = fv::reduce_quote(MODEL, P, fs, K, T, r, qy, th);
-    const double s = fv::bisection_solve(rd.x, rd.beta, queue[j].lo, queue[j].hi, kBisectTol);
+    const double s = fv::bisection_solve(rd.x, rd.beta, rd.bmax, queue[j].lo, queue[j].hi, kBisectTol);
     const double sg = s / rd.sqrtT;
     sig_out[i] = sg;
     if (st_out) st_out[i] = fv::kQOk;
@@ -389,33 +389,37 @@ __device__ __forceinline__ int64_t upper_index(const int64_t* __restrict__ off, 
 }
 
 // Persistent ragged-chain kernel.  Chunks of blockDim*qpt consecutive quotes
-// are dealt round-robin to a grid sized to the device.  For each wave, lane 0
-// locates the maturity (and chain) of the wave's first quote by binary
-// search over the CSR offsets; the other lanes walk forward from it (a
-// maturity holds at least one quote, so the walk is short).
+// are dealt round-robin to a grid sized to the device; inside a chunk every
+// wave owns 64*qpt consecutive quotes and takes them 64 at a time (each step
+// one coalesced 512-byte load per field).  Lane 0 locates the maturity and
+// chain of the wave's first quote by binary search over the CSR offsets;
+// every lane then walks forward from there, and keeps walking from its own
+// previous position for the wave's next 64 quotes (quotes only increase), so
+// the offsets are searched once per wave-chunk.
 template <int SOLVER>
 __global__ __launch_bounds__(kMaxBlock)
-__attribute__((amdgpu_waves_per_eu(FV_SOLVER_WAVES_PER_EU))) void k_iv_chains(KChains c, double* __restrict__ sig_out,
-                            uint8_t* __restrict__ st_out, int qpt) {
+__attribute__((amdgpu_waves_per_eu(FV_SOLVER_WAVES_PER_EU))) void k_iv_chains(
+    KChains c, double* __restrict__ sig_out, uint8_t* __restrict__ st_out, int qpt) {
   const int64_t chunk = (int64_t)blockDim.x * qpt;
   const int64_t n_chunks = (c.n + chunk - 1) / chunk;
+  const int64_t wave_span = 64 * (int64_t)qpt;
+  const int64_t wave_in_block = threadIdx.x >> 6;
   for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
+    const int64_t w0 = ch * chunk + wave_in_block * wave_span;  // wave's first quote
+    if (w0 >= c.n) continue;
+    int64_t m = 0, cc = 0;
+    if (__lane_id() == 0) {
+      m = upper_index(c.mat_quote_off, c.n_mat, w0);
+      cc = upper_index(c.chain_mat_off, c.n_chains, m);
+    }
+    m = __shfl(m, 0);
+    cc = __shfl(cc, 0);
     for (int k = 0; k < qpt; ++k) {
-      const int64_t i = ch * chunk + (int64_t)k * blockDim.x + threadIdx.x;
-      const int64_t i_wave0 = ch * chunk + (int64_t)k * blockDim.x + (threadIdx.x & ~63);
-      if (i_wave0 >= c.n) break;
-      int64_t m0 = 0, c0 = 0;
-      if (__lane_id() == 0) {
-        m0 = upper_index(c.mat_quote_off, c.n_mat, i_wave0);
-        c0 = upper_index(c.chain_mat_off, c.n_chains, m0);
-      }
-      m0 = __shfl(m0, 0);
-      c0 = __shfl(c0, 0);
+      const int64_t i = w0 + (int64_t)k * 64 + __lane_id();
+      if (w0 + (int64_t)k * 64 >= c.n) break;
       if (i >= c.n) continue;
       // bounded walks: malformed offsets cannot index past the arrays
-      int64_t m = m0;
       while (m + 1 < c.n_mat && c.mat_quote_off[m + 1] <= i) ++m;
-      int64_t cc = c0;
       while (cc + 1 < c.n_chains && c.chain_mat_off[cc + 1] <= m) ++cc;
       const double F = c.F[cc], r = c.r[cc], T = c.T[m];
       const double P = c.price[i], K = c.K[i];
@@ -426,13 +430,14 @@ __attribute__((amdgpu_waves_per_eu(FV_SOLVER_WAVES_PER_EU))) void k_iv_chains(KC
       if (st == fv::kQOk) {
         if (SOLVER == FV_SOLVER_LBR) {
           const LbrResult res =
-              fv::lbr_solve(rd.x, rd.beta, kLbrMinSteps, kLbrMaxSteps, kLbrStepTol);
+              fv::lbr_solve(rd.x, rd.beta, rd.bmax, kLbrMinSteps, kLbrMaxSteps, kLbrStepTol);
           sg = res.s / rd.sqrtT;
           if (!res.converged) st = fv::kQNotConverged;
         } else {
-          fv::HalleyState hs = fv::halley_solve(rd.x, rd.beta, kHalleySteps);
+          fv::HalleyState hs = fv::halley_solve(rd.x, rd.beta, rd.bmax, kHalleySteps);
           double s = hs.s;
-          if (!hs.converged) s = fv::bisection_solve(rd.x, rd.beta, hs.lo, hs.hi, kBisectTol);
+          if (!hs.converged)
+            s = fv::bisection_solve(rd.x, rd.beta, rd.bmax, hs.lo, hs.hi, kBisectTol);
           sg = s / rd.sqrtT;
         }
       }
@@ -529,13 +534,15 @@ int fail(int code, const std::string& msg) { return fvh::fail(code, msg); }
 struct LaunchShape {
   int block, qpt;
 };
+// Defaults from timing sweeps on MI355X (the wide-wing 10M-quote batch for
+// the solvers); fv_autotune re-derives them for other shapes of work.
 LaunchShape g_shape[FV_KERNEL_COUNT] = {
     {256, 1},  // price
-    {256, 1},  // IV LBR
-    {256, 1},  // IV Halley
+    {128, 4},  // IV LBR
+    {64, 1},   // IV Halley
     {256, 1},  // Greeks
     {256, 1},  // backward
-    {256, 1},  // chains
+    {128, 4},  // chains
 };
 
 bool valid_shape(int block, int qpt) {

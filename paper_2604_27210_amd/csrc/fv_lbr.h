@@ -27,13 +27,13 @@ __host__ __device__ inline double rational_cubic(double x, double xl, double xr,
                                                  double yr, double dl, double dr, double r) {
   const double D = xr - xl;
   if (!(D > 0.0)) return 0.5 * (yl + yr);
-  double tau = (x - xl) / D;
+  double tau = (x - xl) * rcp_safe(D);  // D may be denormal for deep wings
   tau = fmin(fmax(tau, 0.0), 1.0);
   const double w = 1.0 - tau;
   const double num = yr * tau * tau * tau + (r * yr - D * dr) * tau * tau * w +
                      (r * yl + D * dl) * tau * w * w + yl * w * w * w;
   const double den = 1.0 + (r - 3.0) * tau * w;
-  return num / den;
+  return fdiv(num, den);
 }
 
 // Smallest control parameter that keeps the interpolant monotone
@@ -44,12 +44,12 @@ __host__ __device__ inline double rational_cubic_min_r(double dl, double dr, dou
   const double rmin = -1.0 + 1e-12;
   double r = rmin;
   const bool mono = (dl * S >= 0.0) && (dr * S >= 0.0);
-  if (mono && S != 0.0) r = fmax(r, (dl + dr) / S);
+  if (mono && S != 0.0) r = fmax(r, fdiv(dl + dr, S));
   const bool convex = (dl <= S) && (S <= dr);
   const bool concave = (dl >= S) && (S >= dr);
   if (convex || concave) {
     const double gap = fmin(fabs(dr - S), fabs(S - dl));
-    if (gap > 0.0) r = fmax(r, fabs(dr - dl) / gap);
+    if (gap > 0.0) r = fmax(r, fdiv(fabs(dr - dl), gap));
     else r = fmax(r, 1.0 / kEps);  // degenerate: fall back to (near) linear
   }
   return r;
@@ -60,18 +60,18 @@ __host__ __device__ inline double rational_cubic_min_r(double dl, double dr, dou
 //   y''(xl) = (2/D) [r (S - dl) + dl - dr],   y''(xr) = (2/D) [r (dr - S) + dl - dr].
 __host__ __device__ inline double rational_cubic_r_left(double D, double S, double dl,
                                                         double dr, double c2) {
-  return (0.5 * D * c2 + dr - dl) / (S - dl);
+  return fdiv(0.5 * D * c2 + dr - dl, S - dl);
 }
 __host__ __device__ inline double rational_cubic_r_right(double D, double S, double dl,
                                                          double dr, double c2) {
-  return (0.5 * D * c2 + dr - dl) / (dr - S);
+  return fdiv(0.5 * D * c2 + dr - dl, dr - S);
 }
 
 __host__ __device__ inline double rational_cubic_fit(double x, double xl, double xr,
                                                      double yl, double yr, double dl,
                                                      double dr, double c2, bool fit_left) {
   const double D = xr - xl;
-  const double S = (yr - yl) / D;
+  const double S = (yr - yl) * rcp_safe(D);
   double r = fit_left ? rational_cubic_r_left(D, S, dl, dr, c2)
                       : rational_cubic_r_right(D, S, dl, dr, c2);
   const double rmin = rational_cubic_min_r(dl, dr, S);
@@ -100,23 +100,25 @@ struct LbrResult {
 __host__ __device__ inline double householder3_step(int obj, double x, double s, double beta,
                                                      double inv_ln_beta, double bmax_m_beta,
                                                      const NBlack& nb) {
-  const double is = 1.0 / s;
+  const double is = rcp(s);
   const double x2is2 = x * x * is * is;
   const double eta = x2is2 * is - 0.25 * s;                       // b''/b'
   const double eta3b = eta * eta - 3.0 * x2is2 * is * is - 0.25;  // b'''/b'
   double nu, e2, e3;
   if (obj == kObjMiddle) {
-    nu = (beta - nb.b) / nb.bp;
+    nu = fdiv(beta - nb.b, nb.bp);
     e2 = eta;
     e3 = eta3b;
   } else {
     // lower and upper share one log and one division
     const bool lo = obj == kObjLower;
-    const double w = nb.bp / (lo ? nb.b : nb.c);  // lambda = b'/b  or  mu = b'/(b_max - b)
-    const double L = log(lo ? nb.b : bmax_m_beta / nb.c);
-    const double iw = 1.0 / w;
+    const double den = lo ? nb.b : nb.c;
+    const double iden = rcp(den);
+    const double w = nb.bp * iden;  // lambda = b'/b  or  mu = b'/(b_max - b)
+    const double L = flog(lo ? nb.b : bmax_m_beta * iden);
+    const double iw = rcp(w);
     if (lo) {
-      const double iL = 1.0 / L;
+      const double iL = rcp(L);
       nu = L * (1.0 - L * inv_ln_beta) * iw;
       e2 = eta - w * (1.0 + 2.0 * iL);
       e3 = eta3b - 3.0 * w * eta + 2.0 * w * w - 6.0 * w * (eta - w) * iL + 6.0 * w * w * iL * iL;
@@ -126,7 +128,7 @@ __host__ __device__ inline double householder3_step(int obj, double x, double s,
       e3 = eta3b + 3.0 * w * eta + 2.0 * w * w;
     }
   }
-  double ds = nu * (1.0 + 0.5 * e2 * nu) / (1.0 + nu * (e2 + e3 * nu * (1.0 / 6.0)));
+  double ds = fdiv(nu * (1.0 + 0.5 * e2 * nu), 1.0 + nu * (e2 + e3 * nu * (1.0 / 6.0)));
   if (!(ds == ds)) ds = 0.0;
   return fmax(ds, -0.5 * s);
 }
@@ -147,11 +149,20 @@ __host__ __device__ inline double householder3_step(int obj, double x, double s,
 __host__ __device__ __attribute__((always_inline)) inline double lbr_initial_guess(
     double x, double beta, double bmax, int* obj, uint32_t* trace) {
   const double ax = -x;  // |x|, x <= 0
-  const double sc = sqrt(2.0 * ax);
-  const NBlack nc = normalised_black(x, sc, bmax);
+  // At the inflection point h = -t, so b(s_c) needs one erfcx and no exp:
+  //   b_c = (b_max/2) (1 - erfcx(sqrt|x|)),  b'(s_c) = b_max/sqrt(2 pi).
+  // (For tiny |x| the difference loses ~log10(1/sqrt|x|) digits; b_c only
+  // selects the region and shapes the guess.)
+  const double sax = sqrt(ax);
+  const double sc = kSqrt2 * sax;
+  NBlack nc;
+  nc.b = 0.5 * bmax * (1.0 - erfcx_nonneg(sax));
+  nc.c = bmax - nc.b;
+  nc.bp = kInvSqrt2Pi * bmax;
+  nc.form = kFormErfcx;
   const bool lower_half = beta < nc.b;
   // the other boundary point on the side of beta
-  const double ibc = 1.0 / nc.bp;
+  const double ibc = 1.0 / nc.bp;  // IEEE division: b' may underflow to 0
   const double so = lower_half ? fmax(sc - nc.b * ibc, 0.0) : sc + nc.c * ibc;
   const NBlack no = normalised_black(x, so, bmax);
   const double ibo = 1.0 / no.bp;
@@ -181,16 +192,17 @@ __host__ __device__ __attribute__((always_inline)) inline double lbr_initial_gue
     // (lower map: z = -|x|/(sqrt3 s_l); upper map: z = -s_u/2).  With
     // b''/b' = eta:  df/dbeta = f'/b',  d2f/dbeta2 = (f'' - f' eta)/b'^2.
     const double eta_o = nb_d2_over_d1(x, so);
-    const double z = r1 ? -ax / (kSqrt3 * so) : -0.5 * so;
-    const double ez = exp(-0.5 * z * z);
+    const double iso = rcp(so);
+    const double z = r1 ? -ax * (1.0 / kSqrt3) * iso : -0.5 * so;
+    const double ez = fexp(-0.5 * z * z);
     const double Pz = 0.5 * ez * erfcx_nonneg(-z * kInvSqrt2);  // Phi(z), z <= 0
     const double pz = kInvSqrt2Pi * ez;                          // phi(z)
     double f0, f1, f2;  // f, df/ds, d2f/ds2 at s_o
     if (r1) {
-      const double zp = -z / so;  // dz/ds
+      const double zp = -z * iso;  // dz/ds
       f0 = cl * Pz * Pz * Pz;
       f1 = 3.0 * cl * Pz * Pz * pz * zp;
-      f2 = 3.0 * cl * zp * zp * Pz * pz * (2.0 * pz - Pz * z - 2.0 * Pz / (so * zp));
+      f2 = 3.0 * cl * zp * zp * Pz * pz * (2.0 * pz - Pz * z - 2.0 * Pz * iso * rcp(zp));
     } else {
       f0 = Pz;
       f1 = -0.5 * pz;
@@ -211,9 +223,9 @@ __host__ __device__ __attribute__((always_inline)) inline double lbr_initial_gue
   // invert the map: R1 Phi(z) = (f/cl)^{1/3}, s = -|x|/(sqrt3 z);
   //                 R4 Phi(-s/2) = f,          s = -2 z.
   const double f = fmax(y, 1e-300);
-  const double p = r1 ? fmin(cbrt(f / cl), 0.4999999999) : fmin(f, 0.5);
+  const double p = r1 ? fmin(cbrt(f * rcp(cl)), 0.4999999999) : fmin(f, 0.5);
   const double zi = inv_norm_cdf_lower(p);
-  return r1 ? -ax / (kSqrt3 * zi) : -2.0 * zi;
+  return r1 ? -ax * (1.0 / kSqrt3) * rcp(zi) : -2.0 * zi;
 }
 
 // Full LBR solve: guess, then Householder(3) steps.  `min_steps` steps are
@@ -224,12 +236,11 @@ __host__ __device__ __attribute__((always_inline)) inline double lbr_initial_gue
 // bits 2-3 the number of steps minus 2 and, from bit 8, two bits per step
 // for the evaluation form of that step.
 __host__ __device__ __attribute__((always_inline)) inline LbrResult lbr_solve(
-    double x, double beta, int min_steps, int max_steps, double step_tol,
+    double x, double beta, double bmax, int min_steps, int max_steps, double step_tol,
     uint32_t* trace = nullptr) {
-  const double bmax = exp(0.5 * x);
   int obj;
   double s = lbr_initial_guess(x, beta, bmax, &obj, trace);
-  const double inv_ln_beta = 1.0 / log(beta);
+  const double inv_ln_beta = rcp(flog(beta));
   const double bmax_m_beta = bmax - beta;
   LbrResult res;
   int it = 0;
@@ -256,12 +267,21 @@ struct HalleyState {
 
 // Brenner-Subrahmanyam start s0 = sqrt(2 pi) beta (the at-the-money
 // approximation b(0, s) ~ s/sqrt(2 pi)), then `steps` Halley steps on the
-// direct residual b(s) - beta: step = nu/(1 + eta nu/2), nu = (beta - b)/b'.
-// A bracket [lo, hi] from the sign of the residual keeps every iterate
-// inside; a step that would leave it bisects instead (geometrically).
+// direct residual b(s) - beta: step = nu/(1 + eta nu/2), nu = (beta - b)/b',
+// eta = b''/b'.  Safeguards (the paper does not spell its own out):
+//  * far below the root of an out-of-the-money quote b(s) behaves like
+//    C s^3 exp(-x^2/(2 s^2)), so the curvature term makes the Halley step
+//    crawl (step ~ 2 s^3/x^2).  When the residual is negative and the Halley
+//    factor 1/(1 + eta nu/2) has dropped below 1/2, the step is a Newton step
+//    on ln b - ln beta in u = 1/s^2, where ln b is nearly linear (or, when
+//    b underflowed, to max(2 s, |x|/sqrt(-2 ln beta)), the root of the
+//    leading-order form);
+//  * a bracket [lo, hi] from the sign of the residual keeps every iterate
+//    inside; a step that would leave it bisects instead (geometrically).
 // Converged: last |step| <= 1e-10 s and |b - beta| <= 1e-9 beta.
-__host__ __device__ __attribute__((always_inline)) inline HalleyState halley_solve(double x, double beta, int steps) {
-  const double bmax = exp(0.5 * x);
+__host__ __device__ __attribute__((always_inline)) inline HalleyState halley_solve(
+    double x, double beta, double bmax, int steps) {
+  const double ln_beta = flog(beta);
   HalleyState st;
   st.lo = 0.0;
   st.hi = 1e300;
@@ -271,10 +291,25 @@ __host__ __device__ __attribute__((always_inline)) inline HalleyState halley_sol
     const NBlack nb = normalised_black(x, s, bmax);
     res = nb.b - beta;
     if (res < 0.0) st.lo = s; else st.hi = s;
-    const double nu = -res / nb.bp;
+    const double nu = -res * rcp(nb.bp);
     const double eta = nb_d2_over_d1(x, s);
-    double sn = s + nu / (1.0 + 0.5 * eta * nu);
-    if (!(sn > st.lo && sn < st.hi)) {
+    const double hf = rcp(1.0 + 0.5 * eta * nu);
+    double sn = s + nu * hf;
+    if (res < 0.0 && !(hf >= 0.5) && x < 0.0) {
+      // Newton step on ln b - ln beta in u = 1/s^2, where ln b is close to
+      // linear: d ln b/du = -(b'/b) s^3/2.  If b underflowed or the step is
+      // unusable, the root of the leading-order form b ~ exp(-x^2/(2 s^2)),
+      // but at least 2 s.
+      double un = -1.0;
+      if (nb.b > 0.0) {
+        const double is = rcp(s);
+        const double dLdu = -0.5 * nb.bp * rcp(nb.b) * s * s * s;
+        un = fma(fdiv(ln_beta - flog(nb.b), dLdu), 1.0, is * is);
+      }
+      sn = un > 0.0 ? rsqrt(un) : fmax(2.0 * s, -x * rsqrt(-2.0 * ln_beta));
+    }
+    // inclusive test: at the root the step rounds to 0 and s is a bound
+    if (!(sn >= st.lo && sn <= st.hi)) {
       if (st.hi >= 1e300) sn = 2.0 * s + 1e-3;
       else if (st.lo > 0.0) sn = sqrt(st.lo * st.hi);
       else sn = 0.5 * st.hi;
@@ -288,9 +323,8 @@ __host__ __device__ __attribute__((always_inline)) inline HalleyState halley_sol
 }
 
 // Bisection on ln s inside [lo, hi] until the bracket is below `rel_tol`.
-__host__ __device__ inline double bisection_solve(double x, double beta, double lo,
+__host__ __device__ inline double bisection_solve(double x, double beta, double bmax, double lo,
                                                   double hi, double rel_tol) {
-  const double bmax = exp(0.5 * x);
   if (!(lo > 0.0)) lo = 1e-8;
   if (!(hi < 1e300)) hi = 50.0;
   for (int k = 0; k < 200 && hi - lo > rel_tol * hi; ++k) {

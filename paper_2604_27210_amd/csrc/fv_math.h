@@ -37,10 +37,10 @@ constexpr double kTauSmall = 0.21022410381342863;
 constexpr double kHLarge = -10.0;
 
 // ----------------------------------------------------------- reciprocal
-// 1/x for finite normal x: the hardware estimate v_rcp_f64 refined by two
-// Newton steps (r <- r + r (1 - x r)), within ~1 ulp.  Cheaper than an IEEE
-// division, which also handles denormal and overflowing operands that these
-// call sites never produce.
+// 1/x for finite, normal, non-zero x: the hardware estimate v_rcp_f64
+// refined by two Newton steps (r <- r + r (1 - x r)), within ~1 ulp.  Cheaper
+// than an IEEE division, which also handles zero, infinite and denormal
+// operands: for those the refinement yields NaN (see rcp_safe).
 __host__ __device__ inline double rcp(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
   double r = __builtin_amdgcn_rcp(x);
@@ -50,6 +50,104 @@ __host__ __device__ inline double rcp(double x) {
 #else
   return 1.0 / x;
 #endif
+}
+
+// As rcp, but 1/0 = inf and 1/inf = 0 as for a division (the hardware
+// estimate is exact there and is kept when the refinement turns to NaN).
+__host__ __device__ inline double rcp_safe(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double r0 = __builtin_amdgcn_rcp(x);
+  double r = fma(r0, fma(-x, r0, 1.0), r0);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r == r ? r : r0;
+#else
+  return 1.0 / x;
+#endif
+}
+
+// a/b from the refined reciprocal plus one residual correction (~1 ulp).
+__host__ __device__ inline double fdiv(double a, double b) {
+  const double r = rcp(b);
+  const double q = a * r;
+  return fma(fma(-b, q, a), r, q);
+}
+
+// 1/sqrt(x) for finite positive normal x: v_rsq_f64 refined by two Newton
+// steps y <- y + y (1/2 - x y^2 / 2).
+__host__ __device__ inline double rsqrt(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = fma(y, fma(-hx * y, y, 0.5), y);
+  y = fma(y, fma(-hx * y, y, 0.5), y);
+  return y;
+#else
+  return 1.0 / sqrt(x);
+#endif
+}
+
+// ------------------------------------------------------------ exp / log
+// Lean binary64 exp and log for the solver's finite arguments (the HIP
+// library versions also handle every special input, which these call sites
+// never pass, at two to three times the instruction count).
+//
+// exp: Cody-Waite reduction x = n ln2 + r, |r| <= ln2/2, with ln2 split in a
+// high part exact in binary64 products and a low part; e^r by its Taylor
+// series to degree 13 (truncation < 4e-18 on |r| <= ln2/2); 2^n by ldexp.
+// Arguments below -1000 give 0 (ldexp underflows), NaN propagates.
+constexpr double kLn2Hi = 6.93147180369123816490e-01;  // 0x3FE62E42FEE00000
+constexpr double kLn2Lo = 1.90821492927058770002e-10;  // ln2 - kLn2Hi
+constexpr double kLog2E = 1.44269504088896338700e+00;
+
+__host__ __device__ inline double fexp(double x) {
+  x = x < -1000.0 ? -1000.0 : x;
+  const double n = rint(x * kLog2E);
+  const double r = fma(-n, kLn2Lo, fma(-n, kLn2Hi, x));
+  double p = 1.0 / 6227020800.0;                      // 1/13!
+  p = fma(p, r, 1.0 / 479001600.0);                   // 1/12!
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)n);
+}
+
+// log for positive finite x (0 gives -inf): x = 2^e m with m in
+// [sqrt(1/2), sqrt(2)), f = (m - 1)/(m + 1), ln m = 2 atanh(f) =
+// 2f (1 + f^2/3 + f^4/5 + ...), |f| <= 0.1716 so ten terms reach binary64
+// precision; ln x = e ln2 + ln m with ln2 split as in fexp.
+__host__ __device__ inline double flog(double x) {
+  int e;
+  double m = frexp(x, &e);  // m in [1/2, 1)
+  if (m < 0.70710678118654752440) {
+    m += m;
+    --e;
+  }
+  const double f = (m - 1.0) / (m + 1.0);
+  const double z = f * f;
+  double S = 1.0 / 21.0;
+  S = fma(S, z, 1.0 / 19.0);
+  S = fma(S, z, 1.0 / 17.0);
+  S = fma(S, z, 1.0 / 15.0);
+  S = fma(S, z, 1.0 / 13.0);
+  S = fma(S, z, 1.0 / 11.0);
+  S = fma(S, z, 1.0 / 9.0);
+  S = fma(S, z, 1.0 / 7.0);
+  S = fma(S, z, 1.0 / 5.0);
+  S = fma(S, z, 1.0 / 3.0);
+  const double f2 = f + f;
+  const double de = (double)e;
+  const double lm = fma(f2 * z, S, f2);  // 2f + 2f z S(z)
+  const double res = fma(de, kLn2Hi, fma(de, kLn2Lo, lm));
+  return x == 0.0 ? -__builtin_inf() : res;
 }
 
 // ----------------------------------------------------------------- erfcx
@@ -67,11 +165,11 @@ __host__ __device__ inline double erfcx_nonneg(double z) {
 // Standard normal density and CDF.  Phi goes through erfcx so that the lower
 // tail keeps full relative precision (paper section 2.3 evaluates the CDF
 // through the complementary error function for the same reason).
-__host__ __device__ inline double norm_pdf(double z) { return kInvSqrt2Pi * exp(-0.5 * z * z); }
+__host__ __device__ inline double norm_pdf(double z) { return kInvSqrt2Pi * fexp(-0.5 * z * z); }
 
 __host__ __device__ inline double norm_cdf(double z) {
   const double a = fabs(z) * kInvSqrt2;
-  const double tail = 0.5 * exp(-0.5 * z * z) * erfcx_nonneg(a);  // Phi(-|z|)
+  const double tail = 0.5 * fexp(-0.5 * z * z) * erfcx_nonneg(a);  // Phi(-|z|)
   return z < 0.0 ? tail : 1.0 - tail;
 }
 
@@ -87,16 +185,16 @@ __host__ __device__ inline double inv_norm_cdf_lower(double p) {
       num = fma(num, w, coef::kPhiInvCentralP[i]);
       den = fma(den, w, coef::kPhiInvCentralQ[i]);
     }
-    z = q * num / den;
+    z = q * fdiv(num, den);
   } else {
-    const double r = sqrt(-2.0 * log(p));
+    const double r = sqrt(-2.0 * flog(p));
     double num = coef::kPhiInvTailP[7], den = coef::kPhiInvTailQ[7];
 #pragma unroll
     for (int i = 6; i >= 0; --i) {
       num = fma(num, r, coef::kPhiInvTailP[i]);
       den = fma(den, r, coef::kPhiInvTailQ[i]);
     }
-    z = num / den;
+    z = fdiv(num, den);
   }
   return z;
 }
@@ -153,7 +251,8 @@ __host__ __device__ inline double nb_small_t_ratio(double h, double t, double y0
 
 __host__ __device__ inline double nb_asymptotic_ratio(double h, double t) {
   const double A = -(h + t), B = t - h;
-  const double rho = A / B, a = 1.0 / (A * A);
+  const double iB = rcp(B), iA = rcp(A);
+  const double rho = A * iB, a = iA * iA;  // 1/A^2 may underflow to 0, never inf
   double coefn = 1.0, G = 1.0, rp = rho, sum = 1.0;
   const double onep = 1.0 + rho, rho2 = rho * rho;
 #pragma unroll
@@ -163,7 +262,7 @@ __host__ __device__ inline double nb_asymptotic_ratio(double h, double t) {
     rp *= rho2;
     sum = fma(coefn, G, sum);
   }
-  return 2.0 * t / (A * B) * sum;
+  return 2.0 * t * iA * iB * sum;
 }
 
 // x <= 0, s >= 0, bmax = exp(x/2).  The small-t and erfcx forms share their
@@ -179,7 +278,7 @@ __host__ __device__ inline NBlack normalised_black(double x, double s, double bm
     return r;
   }
   const double h = x * rcp(s), t = 0.5 * s;
-  const double E = exp(-0.5 * fma(h, h, t * t));
+  const double E = fexp(-0.5 * fma(h, h, t * t));
   r.bp = kInvSqrt2Pi * E;
   const bool asym = h < kHLarge && h + t < kHLarge + kTauSmall;
   if (asym) {
@@ -212,11 +311,13 @@ __host__ __device__ inline NBlack normalised_black(double x, double s, double bm
 // b''/b' and b'''/b' as functions of s (closed forms of the derivatives of
 // b'(s) = exp(-(x^2/s^2 + s^2/4)/2)/sqrt(2 pi)).
 __host__ __device__ inline double nb_d2_over_d1(double x, double s) {
-  return x * x / (s * s * s) - 0.25 * s;
+  const double is = rcp(s);
+  return x * x * is * is * is - 0.25 * s;
 }
 __host__ __device__ inline double nb_d3_over_d1(double x, double s, double eta) {
-  const double s2 = s * s;
-  return eta * eta - 3.0 * x * x / (s2 * s2) - 0.25;
+  const double is = rcp(s);
+  const double is2 = is * is;
+  return eta * eta - 3.0 * x * x * is2 * is2 - 0.25;
 }
 
 }  // namespace fv

@@ -32,6 +32,7 @@ enum QuoteStatus : uint8_t {
 struct Reduced {
   double F, D, sqrtT;
   double x, beta;  // normalised out-of-the-money call: x <= 0, 0 < beta < e^{x/2}
+  double bmax;     // e^{x/2} = min(F, K)/sqrt(F K)
   uint8_t status;
 };
 
@@ -41,20 +42,20 @@ __host__ __device__ inline double forward_of(int model, double fs, double T, dou
                                              double q) {
   if (model == kBlack76) return fs;
   const double carry = (model == kBlackScholesMerton) ? (r - q) : r;
-  return fs * exp(carry * T);
+  return fs * fexp(carry * T);
 }
 
 __host__ __device__ inline Reduced reduce_quote(int model, double price, double fs, double K,
                                                 double T, double r, double q, int theta) {
   Reduced o;
-  o.F = 0.0; o.D = 0.0; o.sqrtT = 0.0; o.x = 0.0; o.beta = 0.0;
+  o.F = 0.0; o.D = 0.0; o.sqrtT = 0.0; o.x = 0.0; o.beta = 0.0; o.bmax = 0.0;
   const bool ok_in = finite_d(price) && finite_d(fs) && finite_d(K) && finite_d(T) &&
                      finite_d(r) && finite_d(q) && fs > 0.0 && K > 0.0 && T > 0.0 &&
                      (theta == 1 || theta == -1);
   if (!ok_in) { o.status = kQInvalid; return o; }
   const double F = forward_of(model, fs, T, r, q);
-  const double D = exp(-r * T);
-  const double Pu = price / D;
+  const double D = fexp(-r * T);
+  const double Pu = price * fexp(r * T);
   const double I = theta > 0 ? fmax(F - K, 0.0) : fmax(K - F, 0.0);
   const double M = theta > 0 ? F : K;
   o.F = F;
@@ -64,11 +65,13 @@ __host__ __device__ inline Reduced reduce_quote(int model, double price, double 
   if (Pu == I) { o.status = kQAtIntrinsic; return o; }
   if (Pu >= M) { o.status = kQAboveMax; return o; }
   const int th = (I > 0.0) ? -theta : theta;  // in the money: parity to OTM
-  const double lx = log(F / K);
+  const double lx = flog(F * rcp(K));
   o.x = th > 0 ? lx : -lx;
-  o.beta = (Pu - I) / sqrt(F * K);
+  const double isq = rsqrt(F * K);
+  o.beta = (Pu - I) * isq;
+  o.bmax = fmin(F, K) * isq;
   // the normalised price can round onto its bound even when Pu < M
-  o.status = (o.beta < exp(0.5 * o.x)) ? kQOk : kQAboveMax;
+  o.status = (o.beta < o.bmax) ? kQOk : kQAboveMax;
   return o;
 }
 

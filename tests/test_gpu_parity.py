@@ -164,6 +164,7 @@ def test_ragged_sizes_and_launch_shapes(fv):
         res = compare_iv("bsm", solver, P_all, wl_all.fs, wl_all.K, wl_all.T, wl_all.r,
                          wl_all.q, wl_all.flag, host(s), host(st))
         assert len(res["status_bad"]) == 0 and len(res["value_bad"]) == 0
+    saved = {k: fv.get_launch(k) for k in ("iv_lbr", "iv_halley")}
     try:
         for block, qpt in ((64, 1), (128, 2), (256, 4), (512, 3), (64, 16)):
             fv.set_launch("iv_lbr", block, qpt)
@@ -177,8 +178,8 @@ def test_ragged_sizes_and_launch_shapes(fv):
                     assert torch.equal(torch.nan_to_num(s, nan=-7.0), rs[:n]), (block, qpt, n, solver)
                     assert torch.equal(st, rst[:n]), (block, qpt, n, solver)
     finally:
-        fv.set_launch("iv_lbr", 256, 1)
-        fv.set_launch("iv_halley", 256, 1)
+        for k, (b, q) in saved.items():
+            fv.set_launch(k, b, q)
     # bad shapes are rejected
     from paper_2604_27210_amd._native import FastvolError
     with pytest.raises(FastvolError):
@@ -260,6 +261,7 @@ def test_chains_match_flat_and_oracle(fv):
     ch = W.b76_chains(60, seed=3)
     flat = ch.flatten()
     P = oracle.price("black76", flat.fs, flat.K, flat.T, flat.r, 0.0, flat.sigma_true, flat.flag)
+    saved = fv.get_launch("chains")
     for solver in ("lbr", "halley"):
         for block, qpt in ((256, 1), (128, 4), (512, 2)):
             fv.set_launch("chains", block, qpt)
@@ -276,7 +278,7 @@ def test_chains_match_flat_and_oracle(fv):
             res = compare_iv("black76", solver, P, flat.fs, flat.K, flat.T, flat.r, 0.0 * flat.T,
                              flat.flag, host(sc), host(stc))
             assert len(res["status_bad"]) == 0 and len(res["value_bad"]) == 0
-    fv.set_launch("chains", 256, 1)
+    fv.set_launch("chains", *saved)
 
 
 def test_normalised_black_matches_oracle(fv):
@@ -315,6 +317,8 @@ def test_autotune_picks_a_valid_shape_and_results_do_not_change(fv):
     wl = W.bsm_wide(50_000, seed=21, inject=0.0)
     P = assemble_prices(wl)
     s_ref, st_ref = run_iv(fv, wl, P, "lbr")
+    kernels = ("price", "iv_lbr", "iv_halley", "greeks", "backward", "chains")
+    saved = {k: fv.get_launch(k) for k in kernels}
     try:
         b, q = fv.autotune("iv_lbr", "bsm", 1 << 20)
         assert b % 64 == 0 and 64 <= b <= 512 and 1 <= q <= 16
@@ -325,5 +329,5 @@ def test_autotune_picks_a_valid_shape_and_results_do_not_change(fv):
             b, q = fv.autotune(kern, "black76" if kern == "chains" else "bsm", 1 << 19)
             assert b % 64 == 0 and 1 <= q <= 16
     finally:
-        for kern in ("price", "iv_lbr", "iv_halley", "greeks", "backward", "chains"):
-            fv.set_launch(kern, 256, 1)
+        for k, (b, q) in saved.items():
+            fv.set_launch(k, b, q)
