@@ -36,7 +36,7 @@ if ROOT not in sys.path:
 # ``source_sha256``; the FLOP figure is the algorithmic count of that source.
 LBR_PROFILE = {
     "source_sha256": None,
-    "flop_per_quote": 1549.0,
+    "flop_per_quote": 1260.0,
     "fetch_bytes_per_quote": None,
     "write_bytes_per_quote": None,
 }
@@ -235,13 +235,11 @@ def census(fv, torch, P, S, K, T, r, q, flag):
     fl = flag.index_select(0, order).contiguous()
     times = {}
     for label, ins, f in (("as_generated", (P, S, K, T, r, q), flag), ("sorted_by_path", args, fl)):
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        fv.implied_vol("bsm", ins[0], ins[1], ins[2], ins[3], ins[4], flag=f, q=ins[5], solver="lbr")
-        e1.record()
-        torch.cuda.synchronize()
-        times[label] = e0.elapsed_time(e1)
+        run = lambda: fv.implied_vol("bsm", ins[0], ins[1], ins[2], ins[3], ins[4], flag=f,
+                                     q=ins[5], solver="lbr")
+        # one warm-up launch each, then the median of five timed launches (a
+        # counter run sees 6 dispatches per order: the census reads the last)
+        times[label] = _time(torch, run, reps=5, warm=1)
     c = cs.cpu().numpy().astype(np.uint32)
     solved = c != 0xFFFFFFFF
     region = np.bincount(c[solved] & 3, minlength=4) / solved.sum()

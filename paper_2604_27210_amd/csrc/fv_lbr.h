@@ -27,13 +27,13 @@ __host__ __device__ inline double rational_cubic(double x, double xl, double xr,
                                                  double yr, double dl, double dr, double r) {
   const double D = xr - xl;
   if (!(D > 0.0)) return 0.5 * (yl + yr);
-  double tau = (x - xl) * rcp_safe(D);  // D may be denormal for deep wings
+  double tau = (x - xl) * rcp_lo_safe(D);  // D may be denormal for deep wings
   tau = fmin(fmax(tau, 0.0), 1.0);
   const double w = 1.0 - tau;
   const double num = yr * tau * tau * tau + (r * yr - D * dr) * tau * tau * w +
                      (r * yl + D * dl) * tau * w * w + yl * w * w * w;
   const double den = 1.0 + (r - 3.0) * tau * w;
-  return fdiv(num, den);
+  return fdiv_lo(num, den);
 }
 
 // Smallest control parameter that keeps the interpolant monotone
@@ -44,12 +44,12 @@ __host__ __device__ inline double rational_cubic_min_r(double dl, double dr, dou
   const double rmin = -1.0 + 1e-12;
   double r = rmin;
   const bool mono = (dl * S >= 0.0) && (dr * S >= 0.0);
-  if (mono && S != 0.0) r = fmax(r, fdiv(dl + dr, S));
+  if (mono && S != 0.0) r = fmax(r, fdiv_lo(dl + dr, S));
   const bool convex = (dl <= S) && (S <= dr);
   const bool concave = (dl >= S) && (S >= dr);
   if (convex || concave) {
     const double gap = fmin(fabs(dr - S), fabs(S - dl));
-    if (gap > 0.0) r = fmax(r, fdiv(fabs(dr - dl), gap));
+    if (gap > 0.0) r = fmax(r, fdiv_lo(fabs(dr - dl), gap));
     else r = fmax(r, 1.0 / kEps);  // degenerate: fall back to (near) linear
   }
   return r;
@@ -60,18 +60,18 @@ __host__ __device__ inline double rational_cubic_min_r(double dl, double dr, dou
 //   y''(xl) = (2/D) [r (S - dl) + dl - dr],   y''(xr) = (2/D) [r (dr - S) + dl - dr].
 __host__ __device__ inline double rational_cubic_r_left(double D, double S, double dl,
                                                         double dr, double c2) {
-  return fdiv(0.5 * D * c2 + dr - dl, S - dl);
+  return fdiv_lo(0.5 * D * c2 + dr - dl, S - dl);
 }
 __host__ __device__ inline double rational_cubic_r_right(double D, double S, double dl,
                                                          double dr, double c2) {
-  return fdiv(0.5 * D * c2 + dr - dl, dr - S);
+  return fdiv_lo(0.5 * D * c2 + dr - dl, dr - S);
 }
 
 __host__ __device__ inline double rational_cubic_fit(double x, double xl, double xr,
                                                      double yl, double yr, double dl,
                                                      double dr, double c2, bool fit_left) {
   const double D = xr - xl;
-  const double S = (yr - yl) * rcp_safe(D);
+  const double S = (yr - yl) * rcp_lo_safe(D);
   double r = fit_left ? rational_cubic_r_left(D, S, dl, dr, c2)
                       : rational_cubic_r_right(D, S, dl, dr, c2);
   const double rmin = rational_cubic_min_r(dl, dr, S);
@@ -100,13 +100,13 @@ struct LbrResult {
 __host__ __device__ inline double householder3_step(int obj, double x, double s, double beta,
                                                      double inv_ln_beta, double bmax_m_beta,
                                                      const NBlack& nb) {
-  const double is = rcp(s);
+  const double is = rcp_lo(s);
   const double x2is2 = x * x * is * is;
   const double eta = x2is2 * is - 0.25 * s;                       // b''/b'
   const double eta3b = eta * eta - 3.0 * x2is2 * is * is - 0.25;  // b'''/b'
   double nu, e2, e3;
   if (obj == kObjMiddle) {
-    nu = fdiv(beta - nb.b, nb.bp);
+    nu = fdiv_lo(beta - nb.b, nb.bp);
     e2 = eta;
     e3 = eta3b;
   } else {
@@ -116,9 +116,9 @@ __host__ __device__ inline double householder3_step(int obj, double x, double s,
     const double iden = rcp(den);
     const double w = nb.bp * iden;  // lambda = b'/b  or  mu = b'/(b_max - b)
     const double L = flog(lo ? nb.b : bmax_m_beta * iden);
-    const double iw = rcp(w);
+    const double iw = rcp_lo(w);
     if (lo) {
-      const double iL = rcp(L);
+      const double iL = rcp_lo(L);
       nu = L * (1.0 - L * inv_ln_beta) * iw;
       e2 = eta - w * (1.0 + 2.0 * iL);
       e3 = eta3b - 3.0 * w * eta + 2.0 * w * w - 6.0 * w * (eta - w) * iL + 6.0 * w * w * iL * iL;
@@ -128,7 +128,7 @@ __host__ __device__ inline double householder3_step(int obj, double x, double s,
       e3 = eta3b + 3.0 * w * eta + 2.0 * w * w;
     }
   }
-  double ds = fdiv(nu * (1.0 + 0.5 * e2 * nu), 1.0 + nu * (e2 + e3 * nu * (1.0 / 6.0)));
+  double ds = fdiv_lo(nu * (1.0 + 0.5 * e2 * nu), 1.0 + nu * (e2 + e3 * nu * (1.0 / 6.0)));
   if (!(ds == ds)) ds = 0.0;
   return fmax(ds, -0.5 * s);
 }
@@ -153,19 +153,19 @@ __host__ __device__ __attribute__((always_inline)) inline double lbr_initial_gue
   //   b_c = (b_max/2) (1 - erfcx(sqrt|x|)),  b'(s_c) = b_max/sqrt(2 pi).
   // (For tiny |x| the difference loses ~log10(1/sqrt|x|) digits; b_c only
   // selects the region and shapes the guess.)
-  const double sax = sqrt(ax);
+  const double sax = sqrt_lo(ax);
   const double sc = kSqrt2 * sax;
   NBlack nc;
-  nc.b = 0.5 * bmax * (1.0 - erfcx_nonneg(sax));
+  nc.b = 0.5 * bmax * (1.0 - erfcx_lo(sax));
   nc.c = bmax - nc.b;
   nc.bp = kInvSqrt2Pi * bmax;
-  nc.form = kFormErfcx;
+  nc.form = kFormDifference;
   const bool lower_half = beta < nc.b;
   // the other boundary point on the side of beta
-  const double ibc = 1.0 / nc.bp;  // IEEE division: b' may underflow to 0
+  const double ibc = rcp_lo_safe(nc.bp);  // b' may underflow to 0
   const double so = lower_half ? fmax(sc - nc.b * ibc, 0.0) : sc + nc.c * ibc;
-  const NBlack no = normalised_black(x, so, bmax);
-  const double ibo = 1.0 / no.bp;
+  const NBlack no = normalised_black_t<true>(x, so, bmax);
+  const double ibo = rcp_lo_safe(no.bp);
 
   const bool r1 = lower_half && beta < no.b;
   const bool r4 = !lower_half && beta > no.b;
@@ -191,18 +191,18 @@ __host__ __device__ __attribute__((always_inline)) inline double lbr_initial_gue
     // R1 / R4 share one Phi/phi evaluation at the transformed boundary point
     // (lower map: z = -|x|/(sqrt3 s_l); upper map: z = -s_u/2).  With
     // b''/b' = eta:  df/dbeta = f'/b',  d2f/dbeta2 = (f'' - f' eta)/b'^2.
-    const double eta_o = nb_d2_over_d1(x, so);
-    const double iso = rcp(so);
+    const double iso = rcp_lo(so);
+    const double eta_o = x * x * iso * iso * iso - 0.25 * so;  // b''/b' at s_o
     const double z = r1 ? -ax * (1.0 / kSqrt3) * iso : -0.5 * so;
-    const double ez = fexp(-0.5 * z * z);
-    const double Pz = 0.5 * ez * erfcx_nonneg(-z * kInvSqrt2);  // Phi(z), z <= 0
+    const double ez = fexp_lo(-0.5 * z * z);
+    const double Pz = 0.5 * ez * erfcx_lo(-z * kInvSqrt2);  // Phi(z), z <= 0
     const double pz = kInvSqrt2Pi * ez;                          // phi(z)
     double f0, f1, f2;  // f, df/ds, d2f/ds2 at s_o
     if (r1) {
       const double zp = -z * iso;  // dz/ds
       f0 = cl * Pz * Pz * Pz;
       f1 = 3.0 * cl * Pz * Pz * pz * zp;
-      f2 = 3.0 * cl * zp * zp * Pz * pz * (2.0 * pz - Pz * z - 2.0 * Pz * iso * rcp(zp));
+      f2 = 3.0 * cl * zp * zp * Pz * pz * (2.0 * pz - Pz * z - 2.0 * Pz * iso * rcp_lo(zp));
     } else {
       f0 = Pz;
       f1 = -0.5 * pz;
@@ -223,9 +223,9 @@ __host__ __device__ __attribute__((always_inline)) inline double lbr_initial_gue
   // invert the map: R1 Phi(z) = (f/cl)^{1/3}, s = -|x|/(sqrt3 z);
   //                 R4 Phi(-s/2) = f,          s = -2 z.
   const double f = fmax(y, 1e-300);
-  const double p = r1 ? fmin(cbrt(f * rcp(cl)), 0.4999999999) : fmin(f, 0.5);
+  const double p = r1 ? fmin(cbrt(f * rcp_lo(cl)), 0.4999999999) : fmin(f, 0.5);
   const double zi = inv_norm_cdf_lower(p);
-  return r1 ? -ax * (1.0 / kSqrt3) * rcp(zi) : -2.0 * zi;
+  return r1 ? -ax * (1.0 / kSqrt3) * rcp_lo(zi) : -2.0 * zi;
 }
 
 // Full LBR solve: guess, then Householder(3) steps.  `min_steps` steps are

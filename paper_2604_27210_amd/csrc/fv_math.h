@@ -30,12 +30,6 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kSqrt3 = 1.73205080756887729353;
 constexpr double kEps = 2.220446049250313e-16;
 
-// Branch thresholds of the normalised Black evaluator.
-//   small-t Taylor branch:      t < kTauSmall  (= 2 eps^{1/16})
-//   asymptotic (deep wing):     h < kHLarge and h + t < kHLarge + kTauSmall
-constexpr double kTauSmall = 0.21022410381342863;
-constexpr double kHLarge = -10.0;
-
 // ----------------------------------------------------------- reciprocal
 // 1/x for finite, normal, non-zero x: the hardware estimate v_rcp_f64
 // refined by two Newton steps (r <- r + r (1 - x r)), within ~1 ulp.  Cheaper
@@ -131,7 +125,7 @@ __host__ __device__ inline double flog(double x) {
     m += m;
     --e;
   }
-  const double f = (m - 1.0) / (m + 1.0);
+  const double f = fdiv(m - 1.0, m + 1.0);  // m + 1 in [1.7, 2.5]
   const double z = f * f;
   double S = 1.0 / 21.0;
   S = fma(S, z, 1.0 / 19.0);
@@ -150,15 +144,110 @@ __host__ __device__ inline double flog(double x) {
   return x == 0.0 ? -__builtin_inf() : res;
 }
 
+// ------------------------------------------------ guess-precision helpers
+// The initial guess of the implied-volatility iteration only has to land
+// within ~1e-3 of the root (two quartically convergent steps then reach
+// binary64 precision), and the Householder step itself only needs a relative
+// precision well below its own size.  These variants stop at ~1e-8 relative
+// (one Newton refinement, shorter series) and are used only there; every
+// quantity that decides where the iteration converges -- b(s), its
+// complement, ln b, ln beta -- keeps the full-precision routines.
+__host__ __device__ inline double rcp_lo(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+#else
+  return 1.0 / x;
+#endif
+}
+
+// rcp_lo that keeps the exact 1/0 = inf and 1/inf = 0 of the estimate
+__host__ __device__ inline double rcp_lo_safe(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double r0 = __builtin_amdgcn_rcp(x);
+  const double r = fma(r0, fma(-x, r0, 1.0), r0);
+  return r == r ? r : r0;
+#else
+  return 1.0 / x;
+#endif
+}
+
+__host__ __device__ inline double fdiv_lo(double a, double b) { return a * rcp_lo(b); }
+
+// sqrt(x) for x >= 0 as x / sqrt(x) from the refined reciprocal square root
+__host__ __device__ inline double sqrt_lo(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(y, fma(-0.5 * x * y, y, 0.5), y);
+  return x > 0.0 ? x * y : 0.0;
+#else
+  return sqrt(x);
+#endif
+}
+
+// e^x with the reduction of fexp and the Taylor series to degree 8
+// (truncation < 2.2e-10 on |r| <= ln2/2)
+__host__ __device__ inline double fexp_lo(double x) {
+  x = x < -1000.0 ? -1000.0 : x;
+  const double n = rint(x * kLog2E);
+  const double r = fma(-n, kLn2Lo, fma(-n, kLn2Hi, x));
+  double p = 1.0 / 40320.0;
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)n);
+}
+
+// ln x with the reduction of flog and five terms of the atanh series
+// (truncation < 7e-10 for |f| <= 0.1716)
+__host__ __device__ inline double flog_lo(double x) {
+  int e;
+  double m = frexp(x, &e);
+  if (m < 0.70710678118654752440) {
+    m += m;
+    --e;
+  }
+  const double f = fdiv_lo(m - 1.0, m + 1.0);
+  const double z = f * f;
+  double S = 1.0 / 9.0;
+  S = fma(S, z, 1.0 / 7.0);
+  S = fma(S, z, 1.0 / 5.0);
+  S = fma(S, z, 1.0 / 3.0);
+  const double f2 = f + f;
+  const double de = (double)e;
+  const double res = fma(de, kLn2Hi, fma(f2 * z, S, f2));
+  return x == 0.0 ? -__builtin_inf() : res;
+}
+
 // ----------------------------------------------------------------- erfcx
-// erfcx(z) = exp(z^2) erfc(z) for z >= 0, one branch-free polynomial in
-// y = (z - K)/(z + K) (fitted coefficients, fv_coeffs.h).
-__host__ __device__ inline double erfcx_nonneg(double z) {
-  const double R = rcp(z + coef::kErfcxK);
-  const double y = (z - coef::kErfcxK) * R;
-  double p = coef::kErfcx[23];
+// erfcx(z) = exp(z^2) erfc(z) for z >= -Z0 (Z0 = 1/2), one branch-free
+// polynomial p in y = (z - B + 2 Z0)/(z + B): erfcx(z) = p(y)/(z + B)
+// (fitted coefficients, fv_coeffs.h).
+constexpr int kErfcxDeg = (int)(sizeof(coef::kErfcx) / sizeof(double)) - 1;
+
+__host__ __device__ inline double erfcx_fit(double z) {
+  const double R = rcp(z + coef::kErfcxB);
+  const double y = (z - (coef::kErfcxB - 2.0 * coef::kErfcxZ0)) * R;
+  double p = coef::kErfcx[kErfcxDeg];
 #pragma unroll
-  for (int i = 22; i >= 0; --i) p = fma(p, y, coef::kErfcx[i]);
+  for (int i = kErfcxDeg - 1; i >= 0; --i) p = fma(p, y, coef::kErfcx[i]);
+  return p * R;
+}
+
+// The same form with the guess-precision fit (relative error ~1e-8).
+constexpr int kErfcxLoDeg = (int)(sizeof(coef::kErfcxLo) / sizeof(double)) - 1;
+
+__host__ __device__ inline double erfcx_lo(double z) {
+  const double R = rcp_lo(z + coef::kErfcxLoB);
+  const double y = (z - (coef::kErfcxLoB - 2.0 * coef::kErfcxZ0)) * R;
+  double p = coef::kErfcxLo[kErfcxLoDeg];
+#pragma unroll
+  for (int i = kErfcxLoDeg - 1; i >= 0; --i) p = fma(p, y, coef::kErfcxLo[i]);
   return p * R;
 }
 
@@ -169,143 +258,110 @@ __host__ __device__ inline double norm_pdf(double z) { return kInvSqrt2Pi * fexp
 
 __host__ __device__ inline double norm_cdf(double z) {
   const double a = fabs(z) * kInvSqrt2;
-  const double tail = 0.5 * fexp(-0.5 * z * z) * erfcx_nonneg(a);  // Phi(-|z|)
+  const double tail = 0.5 * fexp(-0.5 * z * z) * erfcx_fit(a);  // Phi(-|z|)
   return z < 0.0 ? tail : 1.0 - tail;
 }
 
-// Inverse standard normal CDF for p in (0, 1/2] (returns a value <= 0).
-// Accurate to ~1e-13 relative; only initial guesses use it.
+// Inverse standard normal CDF for p in (0, 1/2] (returns a value <= 0), as
+// (p - 1/2) P(r)/Q(r) with r = sqrt(-2 ln p): one branch on the whole range,
+// relative error ~5e-8 (fitted, fv_coeffs.h).  Only initial guesses use it.
+constexpr int kPhiInvDegP = (int)(sizeof(coef::kPhiInvP) / sizeof(double)) - 1;
+constexpr int kPhiInvDegQ = (int)(sizeof(coef::kPhiInvQ) / sizeof(double)) - 1;
+
 __host__ __device__ inline double inv_norm_cdf_lower(double p) {
-  double z;
-  if (p >= coef::kPhiInvSplit) {
-    const double q = p - 0.5, w = q * q;
-    double num = coef::kPhiInvCentralP[6], den = coef::kPhiInvCentralQ[6];
+  const double r = sqrt_lo(-2.0 * flog_lo(p));
+  double num = coef::kPhiInvP[kPhiInvDegP], den = coef::kPhiInvQ[kPhiInvDegQ];
 #pragma unroll
-    for (int i = 5; i >= 0; --i) {
-      num = fma(num, w, coef::kPhiInvCentralP[i]);
-      den = fma(den, w, coef::kPhiInvCentralQ[i]);
-    }
-    z = q * fdiv(num, den);
-  } else {
-    const double r = sqrt(-2.0 * flog(p));
-    double num = coef::kPhiInvTailP[7], den = coef::kPhiInvTailQ[7];
+  for (int i = kPhiInvDegP - 1; i >= 0; --i) num = fma(num, r, coef::kPhiInvP[i]);
 #pragma unroll
-    for (int i = 6; i >= 0; --i) {
-      num = fma(num, r, coef::kPhiInvTailP[i]);
-      den = fma(den, r, coef::kPhiInvTailQ[i]);
-    }
-    z = fdiv(num, den);
-  }
-  return z;
+  for (int i = kPhiInvDegQ - 1; i >= 0; --i) den = fma(den, r, coef::kPhiInvQ[i]);
+  return (p - 0.5) * fdiv_lo(num, den);
 }
 
 // ---------------------------------------------------- normalised Black
-// b(x,s)/b'(x,s) = Y(h+t) - Y(h-t) with Y(z) = Phi(z)/phi(z), and
-// b'(x,s) = db/ds = exp(-(h^2+t^2)/2)/sqrt(2 pi).  Three evaluation forms:
+// With q1 = -(h+t)/sqrt2, q2 = (t-h)/sqrt2 >= |q1| (x <= 0) and
+// E = exp(-(h^2+t^2)/2):
+//     b       = E/2 [erfcx(q1) - erfcx(q2)],
+//     b_max-b = E/2 [erfcx(-q1) + erfcx(q2)],
+//     b'      = db/ds = E/sqrt(2 pi).
+// One evaluation form serves every (x, s), so a wave never splits:
 //
-//  * erfcx form: with q1 = -(h+t)/sqrt2, q2 = (t-h)/sqrt2 >= 0 and
-//    E = exp(-(h^2+t^2)/2),
-//        b       = E/2 [erfcx(q1) - erfcx(q2)]     when q1 >= 0,
-//        b_max-b = E/2 [erfcx(-q1) + erfcx(q2)]    when q1 <  0,
-//    so every erfcx argument is >= 0 and the complement b_max - b, which the
-//    upper objective needs, never suffers cancellation.
-//  * small-t form: the odd Taylor series in t of Y(h+t) - Y(h-t),
-//        2 sum_{k odd} t^k Y^{(k)}(h)/k!,
-//    with Y^{(k)} from Y' = 1 + hY, Y^{(k+1)} = h Y^{(k)} + k Y^{(k-1)}; it
-//    removes the cancellation of the erfcx difference when t is small.
-//  * asymptotic form (h << 0): with A = -(h+t), B = t-h, rho = A/B, the
-//    asymptotic series Y(z) ~ sum_n (-1)^n (2n-1)!! |z|^{-(2n+1)} gives
-//        Y(h+t) - Y(h-t) = 2t/(A B) sum_n (-1)^n (2n-1)!! A^{-2n} G_n(rho),
-//        G_n = 1 + rho + ... + rho^{2n},
-//    a sum of positive G_n with an alternating, decreasing asymptotic
-//    factor: no cancellation between A- and B-terms.
+//  * difference form (q1 >= -Z0): the two erfcx values come from the same
+//    polynomial p, so their difference is taken as a divided difference,
+//    never by subtraction.  With R_i = 1/(q_i + B), y_i = p's abscissae,
+//        erfcx(q1) - erfcx(q2) = R1 (p(y1) - p(y2)) + p(y2) (R1 - R2),
+//        y1 - y2 = 2 (B - Z0)(q1 - q2) R1 R2,  R1 - R2 = (q2 - q1) R1 R2,
+//        q1 - q2 = -sqrt2 t,
+//    so  b/b' = sqrt(pi) t R1 R2 [p(y2) - 2 (B - Z0) R1 D],
+//    D = (p(y1) - p(y2))/(y1 - y2) <= 0 from a Horner recurrence that runs
+//    beside the one for p(y2): both terms are >= 0 and nothing cancels, at
+//    any t (this replaces a small-t Taylor branch) and any h (this replaces
+//    an asymptotic deep-wing branch).
+//  * complement form (q1 < -Z0, i.e. h + t > Z0 sqrt2): b_max - b from the
+//    sum above, with erfcx(-q1) from the same recurrence, then
+//    b = b_max - (b_max - b).  Here b >= 0.3 b_max, so the subtraction
+//    loses at most two bits, and the upper objective gets b_max - b
+//    without cancellation.
 struct NBlack {
   double b;   // b(x, s)
   double c;   // b_max - b(x, s)
   double bp;  // db/ds
-  int form;   // evaluation form taken (kFormAsymptotic ... kFormComplement)
+  int form;   // evaluation form taken (kFormDifference or kFormComplement)
 };
 
-enum NbForm : int { kFormAsymptotic = 0, kFormSmallT = 1, kFormErfcx = 2, kFormComplement = 3 };
+enum NbForm : int { kFormDifference = 0, kFormComplement = 1 };
 
-// y0 = Y(h) = sqrt(pi/2) erfcx(-h/sqrt2) for h <= 0.
-__host__ __device__ inline double nb_small_t_ratio(double h, double t, double y0) {
-  double ym = y0;                 // Y^{(k-1)}
-  double yk = fma(h, y0, 1.0);    // Y^{(1)}
-  const double t2 = t * t;
-  // sum_{j>=0} t^{2j} Y^{(2j+1)} / (2j+1)!
-  double sum = yk;
-  double tp = 1.0;                // t^{2j} / (2j+1)!
-#pragma unroll
-  for (int k = 1; k < 17; k += 2) {
-    // advance two orders: Y^{(k+1)}, Y^{(k+2)}
-    const double y1 = fma(h, yk, k * ym);
-    const double y2 = fma(h, y1, (k + 1) * yk);
-    ym = y1;
-    yk = y2;
-    tp *= t2 * (1.0 / ((k + 1) * (k + 2)));
-    sum = fma(tp, yk, sum);
-  }
-  return 2.0 * t * sum;
-}
-
-__host__ __device__ inline double nb_asymptotic_ratio(double h, double t) {
-  const double A = -(h + t), B = t - h;
-  const double iB = rcp(B), iA = rcp(A);
-  const double rho = A * iB, a = iA * iA;  // 1/A^2 may underflow to 0, never inf
-  double coefn = 1.0, G = 1.0, rp = rho, sum = 1.0;
-  const double onep = 1.0 + rho, rho2 = rho * rho;
-#pragma unroll
-  for (int n = 1; n <= 24; ++n) {
-    coefn *= -(2 * n - 1) * a;
-    G = fma(rp, onep, G);
-    rp *= rho2;
-    sum = fma(coefn, G, sum);
-  }
-  return 2.0 * t * iA * iB * sum;
-}
-
-// x <= 0, s >= 0, bmax = exp(x/2).  The small-t and erfcx forms share their
-// first erfcx call (argument -h/sqrt2 or |q1|), so a wave mixing the two
-// forms evaluates two erfcx, not three.
-__host__ __device__ inline NBlack normalised_black(double x, double s, double bmax) {
+// x <= 0, s >= 0, bmax = exp(x/2).  LO = true evaluates at guess precision
+// (erfcx fit of degree 12, shorter exp, one-step reciprocals: ~1e-8
+// relative in b and in b_max - b), for the boundary points of the guess.
+template <bool LO>
+__host__ __device__ inline NBlack normalised_black_t(double x, double s, double bmax) {
   NBlack r;
-  r.form = kFormErfcx;
   if (!(s > 0.0)) {
     r.b = 0.0;
     r.c = bmax;
     r.bp = (x == 0.0) ? kInvSqrt2Pi : 0.0;
+    r.form = kFormDifference;
     return r;
   }
-  const double h = x * rcp(s), t = 0.5 * s;
-  const double E = fexp(-0.5 * fma(h, h, t * t));
+  const double h = x * (LO ? rcp_lo(s) : rcp(s)), t = 0.5 * s;
+  const double ea = -0.5 * fma(h, h, t * t);
+  const double E = LO ? fexp_lo(ea) : fexp(ea);
   r.bp = kInvSqrt2Pi * E;
-  const bool asym = h < kHLarge && h + t < kHLarge + kTauSmall;
-  if (asym) {
-    r.b = r.bp * nb_asymptotic_ratio(h, t);
-    r.c = bmax - r.b;
-    r.form = kFormAsymptotic;
-    return r;
+  const double q1 = -(h + t) * kInvSqrt2, q2 = (t - h) * kInvSqrt2;
+  const bool comp = q1 < -coef::kErfcxZ0;
+  const double z1 = comp ? -q1 : q1;
+  constexpr int kDeg = LO ? kErfcxLoDeg : kErfcxDeg;
+  constexpr const double* kC = LO ? coef::kErfcxLo : coef::kErfcx;
+  constexpr double kB = LO ? coef::kErfcxLoB : coef::kErfcxB;
+  constexpr double kShift = kB - 2.0 * coef::kErfcxZ0;
+  const double R1 = LO ? rcp_lo(z1 + kB) : rcp(z1 + kB);
+  const double R2 = LO ? rcp_lo(q2 + kB) : rcp(q2 + kB);
+  const double y1 = (z1 - kShift) * R1, y2 = (q2 - kShift) * R2;
+  // A = p(y1), B = p(y2), D = (p(y1) - p(y2))/(y1 - y2)
+  double A = kC[kDeg], B = A, D = 0.0;
+#pragma unroll
+  for (int i = kDeg - 1; i >= 0; --i) {
+    D = fma(D, y1, B);
+    A = fma(A, y1, kC[i]);
+    B = fma(B, y2, kC[i]);
   }
-  const bool small = t < kTauSmall;
-  const double q1 = -(h + t) * kInvSqrt2;
-  const double e1 = erfcx_nonneg(small ? -h * kInvSqrt2 : fabs(q1));
-  if (small) {
-    r.b = r.bp * nb_small_t_ratio(h, t, kSqrtPiOver2 * e1);
+  if (!comp) {
+    constexpr double kSqrtPi = 1.77245385090551602730;
+    constexpr double k2BZ = 2.0 * (kB - coef::kErfcxZ0);
+    r.b = r.bp * (kSqrtPi * t * R1 * R2 * fma(-k2BZ * R1, D, B));
     r.c = bmax - r.b;
-    r.form = kFormSmallT;
+    r.form = kFormDifference;
   } else {
-    const double e2 = erfcx_nonneg((t - h) * kInvSqrt2);
-    if (q1 >= 0.0) {
-      r.b = 0.5 * E * (e1 - e2);
-      r.c = bmax - r.b;
-    } else {
-      r.c = 0.5 * E * (e1 + e2);
-      r.b = bmax - r.c;
-      r.form = kFormComplement;
-    }
+    r.c = 0.5 * E * fma(A, R1, B * R2);
+    r.b = bmax - r.c;
+    r.form = kFormComplement;
   }
   return r;
+}
+
+__host__ __device__ inline NBlack normalised_black(double x, double s, double bmax) {
+  return normalised_black_t<false>(x, s, bmax);
 }
 
 // b''/b' and b'''/b' as functions of s (closed forms of the derivatives of

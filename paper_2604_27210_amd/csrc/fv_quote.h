@@ -60,7 +60,14 @@ __host__ __device__ inline Reduced reduce_quote(int model, double price, double 
   const double M = theta > 0 ? F : K;
   o.F = F;
   o.D = D;
-  o.sqrtT = sqrt(T);
+  // sqrt(T) = T / sqrt(T) from the refined reciprocal square root, with T
+  // scaled by 2^200 first when it is so small that v_rsq_f64 could see a
+  // denormal
+  {
+    const bool tiny = T < 1e-290;
+    const double Ts = tiny ? T * 0x1p+200 : T;
+    o.sqrtT = Ts * rsqrt(Ts) * (tiny ? 0x1p-100 : 1.0);
+  }
   if (Pu < I) { o.status = kQBelowIntrinsic; return o; }
   if (Pu == I) { o.status = kQAtIntrinsic; return o; }
   if (Pu >= M) { o.status = kQAboveMax; return o; }

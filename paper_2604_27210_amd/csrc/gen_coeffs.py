@@ -5,23 +5,33 @@ Run:  python gen_coeffs.py   (mpmath; about two minutes)
 Two families of approximations are fitted here, from the mathematical
 definitions evaluated in mpmath (no coefficients are taken from any library):
 
-1. erfcx(z) = exp(z^2) erfc(z) on z >= 0.  With a fixed K, the map
-   y = (z - K)/(z + K) sends [0, inf) to [-1, 1) and the function
-   f(y) = (z + K) erfcx(z) is smooth and bounded on [-1, 1] (it tends to
-   1/sqrt(pi) as z -> inf).  One polynomial in y then covers the whole
-   half-line: erfcx(z) = p(y) / (z + K).  A single branch-free expansion of
-   this kind follows Shepherd & Laframboise, "Chebyshev approximation of
+1. erfcx(z) = exp(z^2) erfc(z) on z >= -Z0 (Z0 = 1/2).  With a fixed B > Z0
+   the map y = (z - B + 2 Z0)/(z + B) sends [-Z0, inf) to [-1, 1) and the
+   function f(y) = (z + B) erfcx(z) is smooth and bounded on [-1, 1] (it
+   tends to 1/sqrt(pi) as z -> inf).  One polynomial in y then covers the
+   whole range: erfcx(z) = p(y) / (z + B).  A single branch-free expansion
+   of this kind follows Shepherd & Laframboise, "Chebyshev approximation of
    (1+2x)exp(x^2)erfc x in 0 <= x < inf", Math. Comp. 36 (1981); the
-   weighting (z + K) instead of (1 + 2z) lets one reciprocal serve both the
-   change of variable and the final scaling.  The coefficients are a
-   relative-error weighted least-squares fit at Chebyshev nodes.
+   weighting (z + B) instead of (1 + 2z) lets one reciprocal serve both the
+   change of variable and the final scaling, and the shifted lower end lets
+   the normalised Black function take the divided difference of two erfcx
+   values whose first argument may be slightly negative.  The coefficients
+   are a relative-error weighted least-squares fit at Chebyshev nodes; the
+   fit is checked for the value and for the derivative p'(y), since the
+   evaluator uses divided differences of p.
 
-2. The inverse standard normal CDF on (0, 1/2], split like Wichura's AS 241
-   (Appl. Stat. 37, 1988) into a central piece z = q P(q^2)/Q(q^2),
-   q = p - 1/2, and a tail piece z = P(r)/Q(r), r = sqrt(-2 ln p).  The
-   rational functions are fitted here by iteratively re-weighted linearised
-   least squares (relative error).  Only the initial guess of the
-   implied-volatility iteration uses them, so ~1e-13 relative is ample.
+   A second, lower-degree fit of the same form (``kErfcxLo``, relative error
+   ~1e-8) serves the initial guess of the implied-volatility iteration,
+   which only has to land within ~1e-3 of the root for two quartically
+   convergent steps to reach binary64 precision.
+
+2. The inverse standard normal CDF on (0, 1/2] (initial guess only), as one
+   rational function in the tail variable r = sqrt(-2 ln p) of the ratio
+   G(r) = Phi^{-1}(p)/(p - 1/2): G -> sqrt(2 pi) at p = 1/2 and grows like
+   2r in the tail, smooth on the whole range, so one branch covers
+   p in [1e-310, 1/2] without the central/tail split of Wichura's AS 241
+   (Appl. Stat. 37, 1988).  Fitted by iteratively re-weighted linearised
+   least squares (relative error ~5e-8, ample for a starting point).
 """
 from __future__ import annotations
 
@@ -29,11 +39,12 @@ import os
 
 import mpmath as mp
 
-ERFCX_K = mp.mpf("3.75")
-ERFCX_DEG = 23
-PHI_INV_SPLIT = mp.mpf("0.075")
-CENTRAL_DEG = (6, 6)
-TAIL_DEG = (7, 7)
+ERFCX_Z0 = mp.mpf("0.5")
+ERFCX_B = mp.mpf("4.25")
+ERFCX_DEG = 25
+ERFCX_LO_B = mp.mpf("3.5")
+ERFCX_LO_DEG = 12
+PHI_INV_DEG = (9, 9)
 P_MIN = mp.mpf("1e-310")
 
 
@@ -66,17 +77,41 @@ def _lstsq(rows, rhs):
     return mp.lu_solve(R[:n, :n], (Q.T * b)[:n, 0])
 
 
-def fit_erfcx():
-    M = 4 * ERFCX_DEG
+def _erfcx_z(y, B):
+    return (B * (1 + y) - 2 * ERFCX_Z0) / (1 - y)
+
+
+def _erfcx_f(y, B):
+    z = _erfcx_z(y, B)
+    return (z + B) * erfcx(z)
+
+
+def fit_erfcx(B, deg):
+    M = 4 * deg
     ys = [mp.cos(mp.pi * (k + mp.mpf(1) / 2) / M) for k in range(M)]
     rows, rhs = [], []
     for y in ys:
-        z = ERFCX_K * (1 + y) / (1 - y)
-        f = (z + ERFCX_K) * erfcx(z)
-        rows.append([y ** j / f for j in range(ERFCX_DEG + 1)])
+        f = _erfcx_f(y, B)
+        rows.append([y ** j / f for j in range(deg + 1)])
         rhs.append(1)
     c = _lstsq(rows, rhs)
-    return [c[j] for j in range(ERFCX_DEG + 1)]
+    return [c[j] for j in range(deg + 1)]
+
+
+def check_erfcx(c, B, n=2000):
+    """Max relative error of p and of p' (coefficients rounded to binary64)
+    on a dense grid of y in (-1, 1)."""
+    cd = [mp.mpf(float(v)) for v in c]
+    dcd = [j * cd[j] for j in range(1, len(cd))]
+    f = lambda y: _erfcx_f(y, B)
+    ev, ed = mp.mpf(0), mp.mpf(0)
+    for k in range(1, n):
+        y = mp.cos(mp.pi * k / n)
+        p = mp.polyval(cd[::-1], y)
+        dp = mp.polyval(dcd[::-1], y)
+        ev = max(ev, abs(p / f(y) - 1))
+        ed = max(ed, abs(dp / mp.diff(f, y) - 1))
+    return ev, ed
 
 
 def fit_rational(ts, fs, m, n, iters=4):
@@ -96,19 +131,26 @@ def fit_rational(ts, fs, m, n, iters=4):
     return P, Q, err
 
 
-def fit_phi_inv():
-    N = 100
+def fit_phi_inv(N=140):
     half = mp.mpf("0.5")
-    qs = [-(half - PHI_INV_SPLIT) * (1 + mp.cos(mp.pi * (k + half) / N)) / 2 for k in range(N)]
-    ts = [q * q for q in qs]
-    fs = [ndtri(q + half) / q for q in qs]
-    cP, cQ, cerr = fit_rational(ts, fs, *CENTRAL_DEG)
-    ra = mp.sqrt(-2 * mp.log(PHI_INV_SPLIT))
+    ra = mp.sqrt(-2 * mp.log(half))
     rb = mp.sqrt(-2 * mp.log(P_MIN))
     rs = [(ra + rb) / 2 + (rb - ra) / 2 * mp.cos(mp.pi * (k + half) / N) for k in range(N)]
-    zs = [ndtri(mp.exp(-r * r / 2)) for r in rs]
-    tP, tQ, terr = fit_rational(rs, zs, *TAIL_DEG)
-    return cP, cQ, cerr, tP, tQ, terr
+    fs = []
+    for r in rs:
+        p = mp.exp(-r * r / 2)
+        fs.append(ndtri(p) / (p - half))
+    P, Q, _ = fit_rational(rs, fs, *PHI_INV_DEG, iters=6)
+    # relative error of Phi^{-1} itself on a dense grid (coefficients rounded)
+    Pd = [mp.mpf(float(v)) for v in P]
+    Qd = [mp.mpf(float(v)) for v in Q]
+    err = mp.mpf(0)
+    for k in range(1, 400):
+        r = ra + (rb - ra) * mp.mpf(k) / 400
+        p = mp.exp(-r * r / 2)
+        g = mp.polyval(Pd[::-1], r) / mp.polyval(Qd[::-1], r)
+        err = max(err, abs(g * (p - half) / ndtri(p) - 1))
+    return P, Q, err
 
 
 def _arr(name, vals):
@@ -118,28 +160,36 @@ def _arr(name, vals):
 
 def main():
     mp.mp.dps = 30
-    ec = fit_erfcx()
-    cP, cQ, cerr, tP, tQ, terr = fit_phi_inv()
+    ec = fit_erfcx(ERFCX_B, ERFCX_DEG)
+    eval_err, deriv_err = check_erfcx(ec, ERFCX_B)
+    el = fit_erfcx(ERFCX_LO_B, ERFCX_LO_DEG)
+    lo_err, lo_deriv = check_erfcx(el, ERFCX_LO_B)
+    pP, pQ, perr = fit_phi_inv()
+    n3 = lambda v: mp.nstr(v, 3)
     out = [
         "// Generated by gen_coeffs.py -- do not edit by hand.\n",
-        "// erfcx(z), z >= 0:  erfcx = p(y)/(z + K),  y = (z - K)/(z + K).\n",
-        "// Inverse normal CDF on (0, 1/2]: central rational in q^2 (p >= split),\n",
-        "// tail rational in r = sqrt(-2 ln p) (p < split).\n",
-        "// central fit max rel err %s, tail fit max rel err %s\n" % (mp.nstr(cerr, 3), mp.nstr(terr, 3)),
+        "// erfcx(z), z >= -Z0:  erfcx = p(y)/(z + B),  y = (z - B + 2 Z0)/(z + B).\n",
+        "// erfcx fit max rel err %s, derivative max rel err %s\n" % (n3(eval_err), n3(deriv_err)),
+        "// guess-precision erfcx (same form, B = kErfcxLoB): max rel err %s, derivative %s\n"
+        % (n3(lo_err), n3(lo_deriv)),
+        "// Inverse normal CDF on (0, 1/2]: Phi^{-1}(p) = (p - 1/2) P(r)/Q(r),\n",
+        "// r = sqrt(-2 ln p); max rel err %s\n" % n3(perr),
         "#pragma once\n\nnamespace fv {\nnamespace coef {\n\n",
-        "constexpr double kErfcxK = %s;\n" % mp.nstr(ERFCX_K, 20),
+        "constexpr double kErfcxZ0 = %s;\n" % mp.nstr(ERFCX_Z0, 20),
+        "constexpr double kErfcxB = %s;\n" % mp.nstr(ERFCX_B, 20),
         _arr("kErfcx", ec),
-        "\nconstexpr double kPhiInvSplit = %s;\n" % mp.nstr(PHI_INV_SPLIT, 20),
-        _arr("kPhiInvCentralP", cP),
-        _arr("kPhiInvCentralQ", cQ),
-        _arr("kPhiInvTailP", tP),
-        _arr("kPhiInvTailQ", tQ),
+        "\nconstexpr double kErfcxLoB = %s;\n" % mp.nstr(ERFCX_LO_B, 20),
+        _arr("kErfcxLo", el),
+        "\n",
+        _arr("kPhiInvP", pP),
+        _arr("kPhiInvQ", pQ),
         "\n}  // namespace coef\n}  // namespace fv\n",
     ]
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "fv_coeffs.h")
     with open(path, "w") as f:
         f.write("".join(out))
-    print("wrote", path, "central err", mp.nstr(cerr, 3), "tail err", mp.nstr(terr, 3))
+    print("wrote", path, "erfcx", n3(eval_err), n3(deriv_err), "erfcx lo", n3(lo_err),
+          n3(lo_deriv), "phi^-1", n3(perr))
 
 
 if __name__ == "__main__":
