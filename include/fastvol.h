@@ -207,18 +207,23 @@ int fv_normalised_black(int64_t n, const double *x, const double *s, const int8_
  * bits 0-1 guess region (0..3 = lower map / lower interior / upper interior /
  * upper map), bits 2-3 Householder(3) steps minus 2, bits 4-5 and 6-7 the
  * normalised-Black evaluation form at the two boundary points, from bit 8
- * two bits per step (forms: 0 asymptotic, 1 small-t, 2 erfcx, 3 erfcx
- * complement).  0xFFFFFFFF for quotes whose status is not FV_Q_OK.  Used to
+ * two bits per step (forms: 0 divided difference of erfcx, 1 complement
+ * b_max - b).  0xFFFFFFFF for quotes whose status is not FV_Q_OK.  Used to
  * group quotes by path, e.g. to measure divergence. */
 int fv_lbr_trace(int model, const fv_quotes *q, uint32_t *path_out, void *stream);
 
 /* Launch-shape control.  fv_set_launch(kernel, block, quotes_per_thread)
  * overrides the launch shape of one kernel family (FV_KERNEL_*); block must
  * be a multiple of 64 in [64, 512] and quotes_per_thread in [1, 16].
- * fv_get_launch reads the current shape.  fv_autotune times the candidate
- * shapes of one kernel family on the given stream with synthetic in-range
- * quotes of size n_hint (the library allocates and frees scratch for this
- * call only -- it is not graph-capturable) and keeps the fastest. */
+ * fv_get_launch reads the current shape.  The shape applies as set to
+ * batches large enough to fill the device; a batch with fewer than two
+ * workgroups per compute unit runs with fewer quotes per thread (halved
+ * until it has two, or one per thread), and with fewer than one workgroup
+ * per compute unit also with 64-thread workgroups.  No result depends on the
+ * shape.  fv_autotune times the candidate shapes (block 64..512, 1..8 quotes
+ * per thread) of one kernel family on the given stream with synthetic
+ * in-range quotes of size n_hint (the library allocates and frees scratch
+ * for this call only -- it is not graph-capturable) and keeps the fastest. */
 enum fv_kernel {
     FV_KERNEL_PRICE = 0,
     FV_KERNEL_IV_LBR = 1,

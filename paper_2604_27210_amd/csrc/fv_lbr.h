@@ -97,9 +97,10 @@ struct LbrResult {
 // nu = -g/g', eta2 = g''/g', eta3 = g'''/g' are written through
 // lambda = b'/b (lower) or mu = b'/(b_max - b) (upper), eta = b''/b' and
 // eta3b = b'''/b'; step = nu (1 + eta2 nu/2) / (1 + nu (eta2 + eta3 nu/6)).
-__host__ __device__ inline double householder3_step(int obj, double x, double s, double beta,
-                                                     double inv_ln_beta, double bmax_m_beta,
-                                                     const NBlack& nb) {
+template <bool LO>
+__host__ __device__ inline double householder3_step_t(int obj, double x, double s, double beta,
+                                                       double inv_ln_beta, double bmax_m_beta,
+                                                       const NBlack& nb) {
   const double is = rcp_lo(s);
   const double x2is2 = x * x * is * is;
   const double eta = x2is2 * is - 0.25 * s;                       // b''/b'
@@ -113,9 +114,10 @@ __host__ __device__ inline double householder3_step(int obj, double x, double s,
     // lower and upper share one log and one division
     const bool lo = obj == kObjLower;
     const double den = lo ? nb.b : nb.c;
-    const double iden = rcp(den);
+    const double iden = LO ? rcp_lo(den) : rcp(den);
     const double w = nb.bp * iden;  // lambda = b'/b  or  mu = b'/(b_max - b)
-    const double L = flog(lo ? nb.b : bmax_m_beta * iden);
+    const double la = lo ? nb.b : bmax_m_beta * iden;
+    const double L = LO ? flog_lo(la) : flog(la);
     const double iw = rcp_lo(w);
     if (lo) {
       const double iL = rcp_lo(L);
@@ -131,6 +133,12 @@ __host__ __device__ inline double householder3_step(int obj, double x, double s,
   double ds = fdiv_lo(nu * (1.0 + 0.5 * e2 * nu), 1.0 + nu * (e2 + e3 * nu * (1.0 / 6.0)));
   if (!(ds == ds)) ds = 0.0;
   return fmax(ds, -0.5 * s);
+}
+
+__host__ __device__ inline double householder3_step(int obj, double x, double s, double beta,
+                                                     double inv_ln_beta, double bmax_m_beta,
+                                                     const NBlack& nb) {
+  return householder3_step_t<false>(obj, x, s, beta, inv_ln_beta, bmax_m_beta, nb);
 }
 
 // Initial guess of the four-region scheme.  Boundary points: the inflection
@@ -243,8 +251,18 @@ __host__ __device__ __attribute__((always_inline)) inline LbrResult lbr_solve(
   const double inv_ln_beta = rcp(flog(beta));
   const double bmax_m_beta = bmax - beta;
   LbrResult res;
+  // The first step starts ~1e-2 from the root and lands ~1e-8 from it, so it
+  // runs at guess precision (b to ~1e-8); every later step is at full
+  // precision and decides the converged root.
   int it = 0;
   double ds = 0.0;
+  if (max_steps > 0) {
+    const NBlack nb = normalised_black_t<true>(x, s, bmax);
+    if (trace) *trace |= (uint32_t)nb.form << 8;
+    ds = householder3_step_t<true>(obj, x, s, beta, inv_ln_beta, bmax_m_beta, nb);
+    s += ds;
+    it = 1;
+  }
   for (; it < max_steps; ++it) {
     if (it >= min_steps && !(fabs(ds) > step_tol * s)) break;
     const NBlack nb = normalised_black(x, s, bmax);
@@ -266,8 +284,8 @@ struct HalleyState {
 };
 
 // Brenner-Subrahmanyam start s0 = sqrt(2 pi) beta (the at-the-money
-// approximation b(0, s) ~ s/sqrt(2 pi)), then `steps` Halley steps on the
-// direct residual b(s) - beta: step = nu/(1 + eta nu/2), nu = (beta - b)/b',
+// approximation b(0, s) ~ s/sqrt(2 pi)), then at most `steps` Halley steps on
+// the direct residual b(s) - beta: step = nu/(1 + eta nu/2), nu = (beta - b)/b',
 // eta = b''/b'.  Safeguards (the paper does not spell its own out):
 //  * far below the root of an out-of-the-money quote b(s) behaves like
 //    C s^3 exp(-x^2/(2 s^2)), so the curvature term makes the Halley step
@@ -278,7 +296,41 @@ struct HalleyState {
 //    leading-order form);
 //  * a bracket [lo, hi] from the sign of the residual keeps every iterate
 //    inside; a step that would leave it bisects instead (geometrically).
+// A lane stops as soon as its step is below 1e-14 s (the root in binary64):
+// a wave whose lanes have all converged leaves the loop early.
 // Converged: last |step| <= 1e-10 s and |b - beta| <= 1e-9 beta.
+__host__ __device__ __attribute__((always_inline)) inline double halley_step(
+    double x, double beta, double bmax, double ln_beta, double s, HalleyState& st,
+    double& res) {
+  const NBlack nb = normalised_black(x, s, bmax);
+  res = nb.b - beta;
+  if (res < 0.0) st.lo = s; else st.hi = s;
+  const double nu = -res * rcp(nb.bp);
+  const double is0 = rcp_lo(s);
+  const double eta = x * x * is0 * is0 * is0 - 0.25 * s;  // b''/b'
+  const double hf = rcp_lo(1.0 + 0.5 * eta * nu);
+  double sn = s + nu * hf;
+  if (res < 0.0 && !(hf >= 0.5) && x < 0.0) {
+    // Newton step on ln b - ln beta in u = 1/s^2, where ln b is close to
+    // linear: d ln b/du = -(b'/b) s^3/2.  If b underflowed (to zero or a
+    // denormal) or the step is unusable, the root of the leading-order form
+    // b ~ exp(-x^2/(2 s^2)), but at least 2 s.
+    double un = -1.0;
+    if (nb.b > 1e-290) {
+      const double dLdu = -0.5 * nb.bp * rcp_lo(nb.b) * s * s * s;
+      un = fma(fdiv_lo(ln_beta - flog(nb.b), dLdu), 1.0, is0 * is0);
+    }
+    sn = (un > 0.0 && un < 1e300) ? rsqrt(un) : fmax(2.0 * s, -x * rsqrt(-2.0 * ln_beta));
+  }
+  // inclusive test: at the root the step rounds to 0 and s is a bound
+  if (!(sn >= st.lo && sn <= st.hi)) {
+    if (st.hi >= 1e300) sn = 2.0 * s + 1e-3;
+    else if (st.lo > 0.0) sn = sqrt(st.lo * st.hi);
+    else sn = 0.5 * st.hi;
+  }
+  return sn;
+}
+
 __host__ __device__ __attribute__((always_inline)) inline HalleyState halley_solve(
     double x, double beta, double bmax, int steps) {
   const double ln_beta = flog(beta);
@@ -288,41 +340,16 @@ __host__ __device__ __attribute__((always_inline)) inline HalleyState halley_sol
   double s = kSqrt2Pi * beta;
   double ds = 0.0, res = 0.0;
   for (int k = 0; k < steps; ++k) {
-    const NBlack nb = normalised_black(x, s, bmax);
-    res = nb.b - beta;
-    if (res < 0.0) st.lo = s; else st.hi = s;
-    const double nu = -res * rcp(nb.bp);
-    const double eta = nb_d2_over_d1(x, s);
-    const double hf = rcp(1.0 + 0.5 * eta * nu);
-    double sn = s + nu * hf;
-    if (res < 0.0 && !(hf >= 0.5) && x < 0.0) {
-      // Newton step on ln b - ln beta in u = 1/s^2, where ln b is close to
-      // linear: d ln b/du = -(b'/b) s^3/2.  If b underflowed or the step is
-      // unusable, the root of the leading-order form b ~ exp(-x^2/(2 s^2)),
-      // but at least 2 s.
-      double un = -1.0;
-      if (nb.b > 0.0) {
-        const double is = rcp(s);
-        const double dLdu = -0.5 * nb.bp * rcp(nb.b) * s * s * s;
-        un = fma(fdiv(ln_beta - flog(nb.b), dLdu), 1.0, is * is);
-      }
-      sn = un > 0.0 ? rsqrt(un) : fmax(2.0 * s, -x * rsqrt(-2.0 * ln_beta));
-    }
-    // inclusive test: at the root the step rounds to 0 and s is a bound
-    if (!(sn >= st.lo && sn <= st.hi)) {
-      if (st.hi >= 1e300) sn = 2.0 * s + 1e-3;
-      else if (st.lo > 0.0) sn = sqrt(st.lo * st.hi);
-      else sn = 0.5 * st.hi;
-    }
+    const double sn = halley_step(x, beta, bmax, ln_beta, s, st, res);
     ds = sn - s;
     s = sn;
+    if (fabs(ds) <= 1e-14 * s) break;
   }
   st.s = s;
   st.converged = fabs(ds) <= 1e-10 * s && fabs(res) <= 1e-9 * beta;
   return st;
 }
 
-// Bisection on ln s inside [lo, hi] until the bracket is below `rel_tol`.
 __host__ __device__ inline double bisection_solve(double x, double beta, double bmax, double lo,
                                                   double hi, double rel_tol) {
   if (!(lo > 0.0)) lo = 1e-8;
