@@ -166,20 +166,24 @@ int fv_implied_vol_chains(int solver, const fv_chains *c, double *sigma_out,
  * sigma_SVI = sqrt(w/T).  The loss is
  *   L = (1/n_quotes) sum_i (IV(P_Black76(sigma_SVI,i)) - iv_target_i)^2,
  * quotes with w <= 1e-10 or a non-finite target contribute nothing; where
- * the model price of sigma_SVI is not solvable in binary64 (it rounded onto
- * its intrinsic value or upper bound) IV(P(sigma_SVI)) takes its exact value
- * sigma_SVI.  chains.price is not read; all arrays are device arrays. */
+ * the model price of sigma_SVI is not solvable in binary64 (its normalised
+ * value rounded onto 0 or onto its upper bound) IV(P(sigma_SVI)) takes its
+ * exact value sigma_SVI.  chains.price is not read; all arrays are device
+ * arrays. */
 typedef struct {
     fv_chains chains;
     const double *iv_target;             /* [n_quotes] */
     double lr, beta1, beta2, eps;        /* Adam hyper-parameters */
 } fv_svi_problem;
 
-/* One Adam step of the calibration, as three launches on `stream` that
+/* One Adam step of the calibration, as two launches on `stream` that
  * allocate nothing and never synchronise (capturable in a hipGraph):
  * per-maturity gradients (one workgroup per maturity; SVI -> Black-76 price
  * -> LBR implied volatility -> implicit-function adjoint, reduced in a fixed
- * order, so results are bitwise reproducible), the Adam update, and the loss.
+ * order, so results are bitwise reproducible), then the Adam update with the
+ * loss.  The price reaches the solver as the normalised price b(x, s) of its
+ * out-of-the-money side, the value the solver's own reduction of the
+ * discounted price recovers.
  *   theta, adam_m, adam_v: [5 n_maturities] in/out (moments start at 0);
  *   step: one device int64 (Adam's step count t, read then incremented);
  *   grad: [5 n_maturities] out, scratch: gradient at the pre-update theta;

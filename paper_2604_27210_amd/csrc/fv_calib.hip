@@ -8,15 +8,22 @@
 //   w(k) = a + b (rho (k - m) + sqrt((k - m)^2 + s^2)),   k = ln(K/F),
 //   sigma_SVI = sqrt(w / T).
 // Loss over the N quotes: L = (1/N) sum (IV(P_B76(sigma_SVI)) - IV_target)^2.
-// One step = three launches, all graph-capturable (no allocation, no host
+// One step = two launches, both graph-capturable (no allocation, no host
 // synchronisation, no memset):
 //   1. one workgroup per maturity: for each quote, SVI -> Black-76 price ->
 //      LBR implied volatility -> residual -> adjoint (dIV/dP = 1/vega(IV),
 //      dP/dsigma = vega(sigma), dsigma/dw = 1/(2 sigma T), dw/dtheta), summed
 //      over the maturity's quotes in registers and then in LDS in a fixed
-//      order (deterministic, no atomics);
-//   2. Adam update of every parameter;
-//   3. deterministic sum of the per-maturity losses and step += 1.
+//      order (deterministic, no atomics); its first thread also advances the
+//      step counter;
+//   2. Adam update of every parameter with the advanced counter; its first
+//      workgroup also sums the per-maturity losses in a fixed order.
+// The price is handed to the solver in the normalised coordinates it
+// reduces every quote to: the Black-76 price of the model is
+// D sqrt(F K) (b(x, s) + intrinsic), and the solver's reduction (undiscount,
+// subtract the intrinsic value, divide by sqrt(F K)) takes it back to
+// beta = b(x, s) exactly in exact arithmetic, so the kernel passes beta = b
+// of the out-of-the-money side to the LBR solve without the round trip.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -42,23 +49,42 @@ struct KSvi {
 __device__ __forceinline__ double softplus(double z) { return z > 30.0 ? z : log1p(exp(z)); }
 __device__ __forceinline__ double sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
 
-struct SviPoint {
-  double w, dw[5];  // total variance and its gradient in the raw parameters
+// Per-maturity constants of the raw parametrisation.
+struct SviMat {
+  double a, b, rho, m, s2, sb, ss;  // sb, ss: softplus' of b~ and s~ (sigmoids)
+  double s;
 };
 
-__device__ __forceinline__ SviPoint svi_eval(const double* th, double k) {
-  const double a = th[0], b = softplus(th[1]), rho = tanh(th[2]), m = th[3],
-               s = softplus(th[4]);
-  const double dk = k - m;
-  const double rt = sqrt(dk * dk + s * s);
-  SviPoint p;
-  p.w = a + b * (rho * dk + rt);
-  p.dw[0] = 1.0;
-  p.dw[1] = (rho * dk + rt) * sigmoid(th[1]);
-  p.dw[2] = b * dk * (1.0 - rho * rho);
-  p.dw[3] = b * (-rho - dk / rt);
-  p.dw[4] = b * (s / rt) * sigmoid(th[4]);
-  return p;
+__device__ __forceinline__ SviMat svi_mat(const double* th) {
+  SviMat q;
+  q.a = th[0];
+  q.b = softplus(th[1]);
+  q.rho = tanh(th[2]);
+  q.m = th[3];
+  q.s = softplus(th[4]);
+  q.s2 = q.s * q.s;
+  q.sb = sigmoid(th[1]);
+  q.ss = sigmoid(th[4]);
+  return q;
+}
+
+// total variance at log-moneyness k
+__device__ __forceinline__ double svi_w(const SviMat& q, double k) {
+  const double dk = k - q.m;
+  return q.a + q.b * (q.rho * dk + sqrt(dk * dk + q.s2));
+}
+
+// g_w * dw/dtheta added into acc[0..4]
+__device__ __forceinline__ void svi_add_grad(const SviMat& q, double k, double g_w,
+                                             double* acc) {
+  const double dk = k - q.m;
+  const double rt = sqrt(dk * dk + q.s2);
+  const double irt = 1.0 / rt;
+  acc[0] += g_w;
+  acc[1] += g_w * (q.rho * dk + rt) * q.sb;
+  acc[2] += g_w * q.b * dk * (1.0 - q.rho * q.rho);
+  acc[3] += g_w * q.b * (-q.rho - dk * irt);
+  acc[4] += g_w * q.b * (q.s * irt) * q.ss;
 }
 
 // Largest c in [0, n_chains) with chain_mat_off[c] <= m.
@@ -71,60 +97,58 @@ __device__ __forceinline__ int64_t chain_of(const int64_t* off, int64_t n_chains
   return lo;
 }
 
-__global__ __launch_bounds__(kCalibBlock) void k_svi_grad(KSvi c, const double* __restrict__ theta,
+__global__ __launch_bounds__(kCalibBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_svi_grad(
+    KSvi c, const double* __restrict__ theta,
                                                           double* __restrict__ grad,
-                                                          double* __restrict__ loss_parts) {
+                                                          double* __restrict__ loss_parts,
+                                                          int64_t* __restrict__ step) {
   __shared__ double red[6][kCalibBlock];
   const int64_t m = blockIdx.x;
   const int64_t ch = chain_of(c.chain_mat_off, c.n_chains, m);
-  const double F = c.F[ch], r = c.r[ch], T = c.T[m];
-  const double D = exp(-r * T), sqT = sqrt(T);
+  const double F = c.F[ch], T = c.T[m];
+  const double sqT = sqrt(T), iT = 1.0 / T;
   double th[5];
 #pragma unroll
   for (int j = 0; j < 5; ++j) th[j] = theta[m * 5 + j];
+  const SviMat q = svi_mat(th);
   const double inv_n = 1.0 / (double)c.n;
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int64_t i = c.mat_quote_off[m] + threadIdx.x; i < c.mat_quote_off[m + 1];
        i += blockDim.x) {
-    const double K = c.K[i];
-    const int fl = c.flag[i];
-    const SviPoint sp = svi_eval(th, log(K / F));
-    if (!(sp.w > kWMin)) continue;
-    const double sigma = sqrt(sp.w / T);
     const double tgt = c.iv_target[i];
-    if (!fv::finite_d(tgt)) continue;
-    const double P = fv::price_at(F, K, D, sigma, sqT, fl);
-    const fv::Reduced rd = fv::reduce_quote(fv::kBlack76, P, F, K, T, r, 0.0, fl);
+    const double lfk = log(F / c.K[i]);  // ln(F/K) = -k
+    const double w = svi_w(q, -lfk);
+    if (!(w > kWMin) || !fv::finite_d(tgt)) continue;
+    const double sigma = sqrt(w * iT);
+    const double s1 = sigma * sqT;
+    // out-of-the-money side: x <= 0, beta = b(x, s1)
+    const double x = -fabs(lfk);
+    const double bmax = exp(0.5 * x);
+    const fv::NBlack nb = fv::normalised_black(x, s1, bmax);
     // IV(P(sigma)) through the LBR solver; where the model price is not
-    // solvable in binary64 (it rounded onto the intrinsic value or the upper
-    // bound) the composite takes its exact value sigma and unit slope
+    // solvable in binary64 (b rounded onto 0 or onto its bound b_max) the
+    // composite takes its exact value sigma and unit slope
     double iv = sigma, ratio = 1.0;
-    if (rd.status == fv::kQOk) {
-      const fv::LbrResult res = fv::lbr_solve(rd.x, rd.beta, rd.bmax, 2, 4, 1e-6);
+    if (nb.b > 0.0 && nb.b < bmax) {
+      const fv::LbrResult res = fv::lbr_solve(x, nb.b, bmax, 2, 4, 1e-6);
       iv = res.s / sqT;
       // vega(v) = D F phi(d1(v)) sqrt(T); only vega(sigma)/vega(iv) enters
-      const double lfk = log(F / K);
-      const double s1 = sigma * sqT, s2 = iv * sqT;
+      const double s2 = res.s;
       const double d1a = lfk / s1 + 0.5 * s1, d1b = lfk / s2 + 0.5 * s2;
       ratio = exp(-0.5 * (d1a * d1a - d1b * d1b));
     }
     const double e = iv - tgt;
-    const double g_sigma = 2.0 * e * inv_n * ratio;
-    const double g_w = g_sigma / (2.0 * sigma * T);
-    acc[0] += g_w * sp.dw[0];
-    acc[1] += g_w * sp.dw[1];
-    acc[2] += g_w * sp.dw[2];
-    acc[3] += g_w * sp.dw[3];
-    acc[4] += g_w * sp.dw[4];
+    const double g_w = e * inv_n * ratio / (sigma * T);  // (2 e/N) ratio / (2 sigma T)
+    svi_add_grad(q, -lfk, g_w, acc);
     acc[5] += e * e;
   }
 #pragma unroll
   for (int j = 0; j < 6; ++j) red[j][threadIdx.x] = acc[j];
   __syncthreads();
-  for (int w = kCalibBlock / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
+  for (int wd = kCalibBlock / 2; wd > 0; wd >>= 1) {
+    if ((int)threadIdx.x < wd) {
 #pragma unroll
-      for (int j = 0; j < 6; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + w];
+      for (int j = 0; j < 6; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + wd];
     }
     __syncthreads();
   }
@@ -132,45 +156,42 @@ __global__ __launch_bounds__(kCalibBlock) void k_svi_grad(KSvi c, const double* 
 #pragma unroll
     for (int j = 0; j < 5; ++j) grad[m * 5 + j] = red[j][0];
     loss_parts[m] = red[5][0];
+    // no other workgroup of this launch reads the counter
+    if (m == 0) *step += 1;
   }
 }
 
-__global__ void k_svi_adam(int64_t n_par, double* __restrict__ theta, double* __restrict__ am,
-                           double* __restrict__ av, const double* __restrict__ grad,
-                           const int64_t* __restrict__ step, double lr, double b1, double b2,
-                           double eps) {
+// Adam with the counter k_svi_grad advanced (t = step, bias corrections
+// 1 - beta^t); workgroup 0 also writes loss[t - 1], the fixed-order sum of
+// the per-maturity losses over N.
+__global__ __launch_bounds__(kCalibBlock) void k_svi_adam(
+    int64_t n_par, double* __restrict__ theta, double* __restrict__ am, double* __restrict__ av,
+    const double* __restrict__ grad, const int64_t* __restrict__ step, double lr, double b1,
+    double b2, double eps, int64_t n_mat, int64_t n, const double* __restrict__ parts,
+    double* __restrict__ loss, int64_t loss_len) {
+  const int64_t t = *step;
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n_par) return;
-  const double t = (double)(*step + 1);
-  const double g = grad[j];
-  const double m = b1 * am[j] + (1.0 - b1) * g;
-  const double v = b2 * av[j] + (1.0 - b2) * g * g;
-  am[j] = m;
-  av[j] = v;
-  const double mh = m / (1.0 - pow(b1, t));
-  const double vh = v / (1.0 - pow(b2, t));
-  theta[j] -= lr * mh / (sqrt(vh) + eps);
-}
-
-__global__ __launch_bounds__(kCalibBlock) void k_svi_finish(int64_t n_mat, int64_t n,
-                                                            const double* __restrict__ parts,
-                                                            double* __restrict__ loss,
-                                                            int64_t loss_len,
-                                                            int64_t* __restrict__ step) {
+  if (j < n_par) {
+    const double g = grad[j];
+    const double mo = b1 * am[j] + (1.0 - b1) * g;
+    const double v = b2 * av[j] + (1.0 - b2) * g * g;
+    am[j] = mo;
+    av[j] = v;
+    const double mh = mo / (1.0 - pow(b1, (double)t));
+    const double vh = v / (1.0 - pow(b2, (double)t));
+    theta[j] -= lr * mh / (sqrt(vh) + eps);
+  }
+  if (blockIdx.x != 0) return;
   __shared__ double red[kCalibBlock];
   double a = 0.0;
-  for (int64_t m = threadIdx.x; m < n_mat; m += blockDim.x) a += parts[m];
+  for (int64_t mm = threadIdx.x; mm < n_mat; mm += blockDim.x) a += parts[mm];
   red[threadIdx.x] = a;
   __syncthreads();
-  for (int w = kCalibBlock / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+  for (int wd = kCalibBlock / 2; wd > 0; wd >>= 1) {
+    if ((int)threadIdx.x < wd) red[threadIdx.x] += red[threadIdx.x + wd];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const int64_t t = *step;
-    if (loss && t >= 0 && t < loss_len) loss[t] = red[0] / (double)n;
-    *step = t + 1;
-  }
+  if (threadIdx.x == 0 && loss && t >= 1 && t <= loss_len) loss[t - 1] = red[0] / (double)n;
 }
 
 __global__ void k_svi_vols(KSvi c, const double* __restrict__ theta, double* __restrict__ out) {
@@ -181,10 +202,11 @@ __global__ void k_svi_vols(KSvi c, const double* __restrict__ theta, double* __r
   double th[5];
 #pragma unroll
   for (int j = 0; j < 5; ++j) th[j] = theta[m * 5 + j];
+  const SviMat q = svi_mat(th);
   for (int64_t i = c.mat_quote_off[m] + threadIdx.x; i < c.mat_quote_off[m + 1];
        i += blockDim.x) {
-    const SviPoint sp = svi_eval(th, log(c.K[i] / F));
-    out[i] = sp.w > 0.0 ? sqrt(sp.w / T) : __builtin_nan("");
+    const double w = svi_w(q, log(c.K[i] / F));
+    out[i] = w > 0.0 ? sqrt(w / T) : __builtin_nan("");
   }
 }
 
@@ -233,12 +255,12 @@ int fv_svi_adam_step(const fv_svi_problem* p, double* theta, double* adam_m, dou
     return fvh::fail(FV_E_INVALID_ARG, "Adam hyper-parameters out of range");
   const KSvi k = to_k(p);
   hipStream_t s = (hipStream_t)stream;
-  k_svi_grad<<<dim3((unsigned)k.n_mat), dim3(kCalibBlock), 0, s>>>(k, theta, grad, loss_parts);
+  k_svi_grad<<<dim3((unsigned)k.n_mat), dim3(kCalibBlock), 0, s>>>(k, theta, grad, loss_parts,
+                                                                   step);
   const int64_t n_par = 5 * k.n_mat;
-  k_svi_adam<<<dim3((unsigned)((n_par + 255) / 256)), dim3(256), 0, s>>>(
-      n_par, theta, adam_m, adam_v, grad, step, p->lr, p->beta1, p->beta2, p->eps);
-  k_svi_finish<<<dim3(1), dim3(kCalibBlock), 0, s>>>(k.n_mat, k.n, loss_parts, loss, loss_len,
-                                                    step);
+  k_svi_adam<<<dim3((unsigned)((n_par + kCalibBlock - 1) / kCalibBlock)), dim3(kCalibBlock), 0, s>>>(
+      n_par, theta, adam_m, adam_v, grad, step, p->lr, p->beta1, p->beta2, p->eps, k.n_mat, k.n,
+      loss_parts, loss, loss_len);
   return fvh::launched("fv_svi_adam_step");
 }
 
