@@ -77,6 +77,10 @@ def parse():
                          "then run the LBR kernel once on the workload as generated and once "
                          "with quotes sorted by path, so that FP64 instruction counters "
                          "(rocprofv3 --pmc) of the sorted launch give the algorithmic work")
+    ap.add_argument("--n-sweep", action="store_true",
+                    help="instead of the bench: throughput of LBR and Halley IV, pricing and "
+                         "Greeks on the first N quotes of the wide workload, N = 1e3 .. 1e8 "
+                         "(one JSON line per N)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="instead of the bench: copy a 1 GiB device buffer three times "
                          "(the reference launch that scales FETCH_SIZE / WRITE_SIZE to bytes)")
@@ -227,6 +231,38 @@ def extras(fv, torch, main_inputs):
     return out
 
 
+def n_sweep(fv, torch):
+    """Throughput against batch size on prefixes of one 10^8-quote draw of
+    the wide BSM workload (prices from the library's pricer, no injected
+    quotes): where launch latency stops dominating and where each path
+    saturates the device."""
+    from paper_2604_27210_amd import workloads as W
+    n_max = 100_000_000
+    wl = W.bsm_wide(n_max, seed=2, inject=0.0)
+    d = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt)
+    S, K, T, r, q, sg = (d(x) for x in (wl.fs, wl.K, wl.T, wl.r, wl.q, wl.sigma_true))
+    flag = d(wl.flag, torch.int8)
+    del wl
+    P = fv.price("bsm", S, K, T, r, sg, flag=flag, q=q)
+    torch.cuda.synchronize()
+    for n in (1_000, 10_000, 100_000, 1_000_000, 10_000_000, 100_000_000):
+        a = [x[:n] for x in (P, S, K, T, r, q, sg)]
+        fl = flag[:n]
+        reps = 50 if n <= 1_000_000 else (10 if n <= 10_000_000 else 5)
+        row = {"n_sweep": True, "n": n}
+        for name, fn in (
+                ("lbr", lambda: fv.implied_vol("bsm", a[0], a[1], a[2], a[3], a[4], flag=fl, q=a[5],
+                                               solver="lbr")),
+                ("halley", lambda: fv.implied_vol("bsm", a[0], a[1], a[2], a[3], a[4], flag=fl,
+                                                  q=a[5], solver="halley")),
+                ("price", lambda: fv.price("bsm", a[1], a[2], a[3], a[4], a[6], flag=fl, q=a[5])),
+                ("greeks", lambda: fv.greeks("bsm", a[1], a[2], a[3], a[4], a[6], flag=fl, q=a[5]))):
+            ms = _time(torch, fn, reps=reps, warm=2)
+            row[name + "_ms"] = ms
+            row[name + "_per_s"] = n / ms * 1e3
+        print(json.dumps(row), flush=True)
+
+
 def census(fv, torch, P, S, K, T, r, q, flag):
     code = fv.lbr_trace("bsm", P, S, K, T, r, flag=flag, q=q)
     order = torch.argsort(code.to(torch.int64))
@@ -265,6 +301,9 @@ def main():
     import paper_2604_27210_amd as fv
     fv._native.load()
     torch.cuda.init()
+    if a.n_sweep:
+        n_sweep(fv, torch)
+        return
     wl, P, S, K, T, r, q, flag = make_inputs(a.n, torch, fv)
     stream = torch.cuda.current_stream()
     if a.census:

@@ -130,7 +130,10 @@ __global__ __launch_bounds__(kCalibBlock) __attribute__((amdgpu_waves_per_eu(3))
     // composite takes its exact value sigma and unit slope
     double iv = sigma, ratio = 1.0;
     if (nb.b > 0.0 && nb.b < bmax) {
-      const fv::LbrResult res = fv::lbr_solve(x, nb.b, bmax, 2, 4, 1e-6);
+      // ln beta from the evaluator's logarithmic parts (accurate also where
+      // b is below the normal range)
+      const double ln_beta = nb.lnbp + fv::flog(nb.ratio);
+      const fv::LbrResult res = fv::lbr_solve(x, nb.b, bmax, ln_beta, 2, 4, 1e-6);
       iv = res.s / sqT;
       // vega(v) = D F phi(d1(v)) sqrt(T); only vega(sigma)/vega(iv) enters
       const double s2 = res.s;

@@ -70,10 +70,13 @@ struct GreekOut {
 // Largest workgroup the kernels are compiled for (8 waves).
 constexpr int kMaxBlock = 512;
 // Minimum resident waves per SIMD the solver kernels are register-allocated
-// for (2: up to 256 VGPRs, 3: 168, 4: 128).
+// for (2: up to 256 VGPRs, 3: 168, 4: 128).  The plain solver kernels fit 4
+// without spilling; their fused-Greeks variants keep more live values and
+// are held at 2 so that they do not spill.
 #ifndef FV_SOLVER_WAVES_PER_EU
-#define FV_SOLVER_WAVES_PER_EU 2
+#define FV_SOLVER_WAVES_PER_EU 4
 #endif
+#define FV_WAVES(GREEKS) ((GREEKS) ? 2 : FV_SOLVER_WAVES_PER_EU)
 // The ragged kernel keeps its CSR windows live across the solve; held to the
 // flat kernel's 4 waves per SIMD (<= 128 VGPRs).
 #ifndef FV_CHAINS_WAVES_PER_EU
@@ -112,7 +115,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_price(KQuotes q, fv_arg sigma, do
 // ------------------------------------------------------------- IV: LBR
 template <int MODEL, bool GREEKS>
 __global__ __launch_bounds__(kMaxBlock)
-__attribute__((amdgpu_waves_per_eu(FV_SOLVER_WAVES_PER_EU))) void k_iv_lbr(KQuotes q, double* __restrict__ sig_out, uint8_t* __restrict__ st_out,
+__attribute__((amdgpu_waves_per_eu(FV_WAVES(GREEKS)))) void k_iv_lbr(KQuotes q, double* __restrict__ sig_out, uint8_t* __restrict__ st_out,
                          GreekOut g, int qpt) {
   const int64_t base = (int64_t)blockIdx.x * blockDim.x * qpt + threadIdx.x;
   for (int k = 0; k < qpt; ++k) {
@@ -126,7 +129,7 @@ __attribute__((amdgpu_waves_per_eu(FV_SOLVER_WAVES_PER_EU))) void k_iv_lbr(KQuot
     uint8_t st = rd.status;
     double sg = st == fv::kQAtIntrinsic ? 0.0 : __builtin_nan("");
     if (st == fv::kQOk) {
-      const LbrResult res = fv::lbr_solve(rd.x, rd.beta, rd.bmax, kLbrMinSteps, kLbrMaxSteps, kLbrStepTol);
+      const LbrResult res = fv::lbr_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kLbrMinSteps, kLbrMaxSteps, kLbrStepTol);
       sg = res.s / rd.sqrtT;
       if (!res.converged) st = fv::kQNotConverged;
     }
@@ -165,7 +168,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_lbr_trace(KQuotes q, uint32_t* __
     uint32_t code = 0xFFFFFFFFu;  // not solved (status != OK)
     if (rd.status == fv::kQOk) {
       code = 0;
-      fv::lbr_solve(rd.x, rd.beta, rd.bmax, kLbrMinSteps, kLbrMaxSteps, kLbrStepTol, &code);
+      fv::lbr_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kLbrMinSteps, kLbrMaxSteps, kLbrStepTol, &code);
     }
     out[i] = code;
   }
@@ -185,7 +188,7 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 
 template <int MODEL, bool GREEKS>
 __global__ __launch_bounds__(kMaxBlock)
-__attribute__((amdgpu_waves_per_eu(FV_SOLVER_WAVES_PER_EU))) void k_iv_halley(KQuotes q, double* __restrict__ sig_out,
+__attribute__((amdgpu_waves_per_eu(FV_WAVES(GREEKS)))) void k_iv_halley(KQuotes q, double* __restrict__ sig_out,
                             uint8_t* __restrict__ st_out, GreekOut g, int qpt) {
   extern __shared__ unsigned char smem_raw[];
   Pending* queue = reinterpret_cast<Pending*>(smem_raw);
@@ -209,7 +212,7 @@ __attribute__((amdgpu_waves_per_eu(FV_SOLVER_WAVES_PER_EU))) void k_iv_halley(KQ
       uint8_t st = rd.status;
       double sg = st == fv::kQAtIntrinsic ? 0.0 : __builtin_nan("");
       if (st == fv::kQOk) {
-        hs = fv::halley_solve(rd.x, rd.beta, rd.bmax, kHalleySteps);
+        hs = fv::halley_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kHalleySteps);
         sg = hs.s / rd.sqrtT;
         fail = !hs.converged;
       }
@@ -491,11 +494,11 @@ __attribute__((amdgpu_waves_per_eu(FV_CHAINS_WAVES_PER_EU))) void k_iv_chains(
       if (st == fv::kQOk) {
         if (SOLVER == FV_SOLVER_LBR) {
           const LbrResult res =
-              fv::lbr_solve(rd.x, rd.beta, rd.bmax, kLbrMinSteps, kLbrMaxSteps, kLbrStepTol);
+              fv::lbr_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kLbrMinSteps, kLbrMaxSteps, kLbrStepTol);
           sg = res.s / rd.sqrtT;
           if (!res.converged) st = fv::kQNotConverged;
         } else {
-          fv::HalleyState hs = fv::halley_solve(rd.x, rd.beta, rd.bmax, kHalleySteps);
+          fv::HalleyState hs = fv::halley_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kHalleySteps);
           double s = hs.s;
           if (!hs.converged)
             s = fv::bisection_solve(rd.x, rd.beta, rd.bmax, hs.lo, hs.hi, kBisectTol);

@@ -111,14 +111,16 @@ __host__ __device__ inline double householder3_step_t(int obj, double x, double 
     e2 = eta;
     e3 = eta3b;
   } else {
-    // lower and upper share one log and one division
+    // lower and upper share one log and one division.  The lower objective
+    // works in logarithms: ln b = ln b' + ln(b/b') and lambda = b'/b =
+    // 1/(b/b'), which stay accurate where b itself has left the normal range.
     const bool lo = obj == kObjLower;
-    const double den = lo ? nb.b : nb.c;
+    const double den = lo ? nb.ratio : nb.c;
     const double iden = LO ? rcp_lo(den) : rcp(den);
-    const double w = nb.bp * iden;  // lambda = b'/b  or  mu = b'/(b_max - b)
-    const double la = lo ? nb.b : bmax_m_beta * iden;
-    const double L = LO ? flog_lo(la) : flog(la);
-    const double iw = rcp_lo(w);
+    const double w = lo ? iden : nb.bp * iden;  // lambda = b'/b  or  mu = b'/(b_max - b)
+    const double la = lo ? nb.ratio : bmax_m_beta * iden;
+    const double L = (LO ? flog_lo(la) : flog(la)) + (lo ? nb.lnbp : 0.0);
+    const double iw = lo ? nb.ratio : rcp_lo(w);
     if (lo) {
       const double iL = rcp_lo(L);
       nu = L * (1.0 - L * inv_ln_beta) * iw;
@@ -155,7 +157,7 @@ __host__ __device__ inline double householder3_step(int obj, double x, double s,
 // `trace` (may be NULL) receives the path taken: bits 0-1 the guess region
 // (0..3 for R1..R4), bits 4-5 and 6-7 the evaluation forms at s_c and s_o.
 __host__ __device__ __attribute__((always_inline)) inline double lbr_initial_guess(
-    double x, double beta, double bmax, int* obj, uint32_t* trace) {
+    double x, double beta, double bmax, double ln_beta, int* obj, uint32_t* trace) {
   const double ax = -x;  // |x|, x <= 0
   // At the inflection point h = -t, so b(s_c) needs one erfcx and no exp:
   //   b_c = (b_max/2) (1 - erfcx(sqrt|x|)),  b'(s_c) = b_max/sqrt(2 pi).
@@ -230,9 +232,19 @@ __host__ __device__ __attribute__((always_inline)) inline double lbr_initial_gue
   if (!wing) return y;
   // invert the map: R1 Phi(z) = (f/cl)^{1/3}, s = -|x|/(sqrt3 z);
   //                 R4 Phi(-s/2) = f,          s = -2 z.
+  // The lower-map cubic leaves (0, 0) with slope 1, so for a beta below the
+  // normal range f = beta (1 + O(beta)): then ln p = (ln beta - ln cl)/3 is
+  // taken from ln beta, which stays finite where f and p underflow.
   const double f = fmax(y, 1e-300);
-  const double p = r1 ? fmin(cbrt(f * rcp_lo(cl)), 0.4999999999) : fmin(f, 0.5);
-  const double zi = inv_norm_cdf_lower(p);
+  double p = r1 ? fmin(cbrt(f * rcp_lo(cl)), 0.4999999999) : fmin(f, 0.5);
+  double lnp;
+  if (r1 && y < 0x1p-960) {
+    lnp = (ln_beta - flog_lo(cl)) * (1.0 / 3.0);
+    p = 0.0;
+  } else {
+    lnp = flog_lo(p);
+  }
+  const double zi = inv_norm_cdf_lower_ln(p, lnp);
   return r1 ? -ax * (1.0 / kSqrt3) * rcp_lo(zi) : -2.0 * zi;
 }
 
@@ -244,11 +256,11 @@ __host__ __device__ __attribute__((always_inline)) inline double lbr_initial_gue
 // bits 2-3 the number of steps minus 2 and, from bit 8, two bits per step
 // for the evaluation form of that step.
 __host__ __device__ __attribute__((always_inline)) inline LbrResult lbr_solve(
-    double x, double beta, double bmax, int min_steps, int max_steps, double step_tol,
-    uint32_t* trace = nullptr) {
+    double x, double beta, double bmax, double ln_beta, int min_steps, int max_steps,
+    double step_tol, uint32_t* trace = nullptr) {
   int obj;
-  double s = lbr_initial_guess(x, beta, bmax, &obj, trace);
-  const double inv_ln_beta = rcp(flog(beta));
+  double s = lbr_initial_guess(x, beta, bmax, ln_beta, &obj, trace);
+  const double inv_ln_beta = rcp(ln_beta);
   const double bmax_m_beta = bmax - beta;
   LbrResult res;
   // The first step starts ~1e-2 from the root and lands ~1e-8 from it, so it
@@ -325,15 +337,14 @@ __host__ __device__ __attribute__((always_inline)) inline double halley_step(
   // inclusive test: at the root the step rounds to 0 and s is a bound
   if (!(sn >= st.lo && sn <= st.hi)) {
     if (st.hi >= 1e300) sn = 2.0 * s + 1e-3;
-    else if (st.lo > 0.0) sn = sqrt(st.lo * st.hi);
+    else if (st.lo > 0.0) sn = sqrt(st.lo) * sqrt(st.hi);  // no underflow of lo hi
     else sn = 0.5 * st.hi;
   }
   return sn;
 }
 
 __host__ __device__ __attribute__((always_inline)) inline HalleyState halley_solve(
-    double x, double beta, double bmax, int steps) {
-  const double ln_beta = flog(beta);
+    double x, double beta, double bmax, double ln_beta, int steps) {
   HalleyState st;
   st.lo = 0.0;
   st.hi = 1e300;
@@ -354,12 +365,13 @@ __host__ __device__ inline double bisection_solve(double x, double beta, double 
                                                   double hi, double rel_tol) {
   if (!(lo > 0.0)) lo = 1e-8;
   if (!(hi < 1e300)) hi = 50.0;
+  // geometric midpoints as sqrt(lo) sqrt(hi): lo hi may underflow
   for (int k = 0; k < 200 && hi - lo > rel_tol * hi; ++k) {
-    const double mid = sqrt(lo * hi);
+    const double mid = sqrt(lo) * sqrt(hi);
     const NBlack nb = normalised_black(x, mid, bmax);
     if (nb.b < beta) lo = mid; else hi = mid;
   }
-  return sqrt(lo * hi);
+  return sqrt(lo) * sqrt(hi);
 }
 
 }  // namespace fv

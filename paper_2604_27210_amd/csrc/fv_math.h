@@ -26,6 +26,7 @@ constexpr double kInvSqrt2 = 0.70710678118654752440;
 constexpr double kSqrt2Pi = 2.50662827463100050242;
 constexpr double kInvSqrt2Pi = 0.39894228040143267794;
 constexpr double kSqrtPiOver2 = 1.25331413731550025121;
+constexpr double kLnSqrt2Pi = 0.91893853320467274178;
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kSqrt3 = 1.73205080756887729353;
 constexpr double kEps = 2.220446049250313e-16;
@@ -268,6 +269,18 @@ __host__ __device__ inline double norm_cdf(double z) {
 constexpr int kPhiInvDegP = (int)(sizeof(coef::kPhiInvP) / sizeof(double)) - 1;
 constexpr int kPhiInvDegQ = (int)(sizeof(coef::kPhiInvQ) / sizeof(double)) - 1;
 
+// p in (0, 1/2] with its logarithm lnp (which stays finite when p
+// underflows: then p - 1/2 is -1/2).
+__host__ __device__ inline double inv_norm_cdf_lower_ln(double p, double lnp) {
+  const double r = sqrt_lo(-2.0 * lnp);
+  double num = coef::kPhiInvP[kPhiInvDegP], den = coef::kPhiInvQ[kPhiInvDegQ];
+#pragma unroll
+  for (int i = kPhiInvDegP - 1; i >= 0; --i) num = fma(num, r, coef::kPhiInvP[i]);
+#pragma unroll
+  for (int i = kPhiInvDegQ - 1; i >= 0; --i) den = fma(den, r, coef::kPhiInvQ[i]);
+  return (p - 0.5) * fdiv_lo(num, den);
+}
+
 __host__ __device__ inline double inv_norm_cdf_lower(double p) {
   const double r = sqrt_lo(-2.0 * flog_lo(p));
   double num = coef::kPhiInvP[kPhiInvDegP], den = coef::kPhiInvQ[kPhiInvDegQ];
@@ -302,11 +315,16 @@ __host__ __device__ inline double inv_norm_cdf_lower(double p) {
 //    b = b_max - (b_max - b).  Here b >= 0.3 b_max, so the subtraction
 //    loses at most two bits, and the upper objective gets b_max - b
 //    without cancellation.
+//  b and b' themselves leave the normal range deep in the wing (b below
+//  2^-1022 keeps fewer significant bits); b/b' and ln b' do not, so ln b is
+//  formed as ln b' + ln(b/b') where the logarithmic objective needs it.
 struct NBlack {
-  double b;   // b(x, s)
-  double c;   // b_max - b(x, s)
-  double bp;  // db/ds
-  int form;   // evaluation form taken (kFormDifference or kFormComplement)
+  double b;      // b(x, s)
+  double c;      // b_max - b(x, s)
+  double bp;     // db/ds
+  double ratio;  // b / b' (difference form; b/b' from b in the complement form)
+  double lnbp;   // ln b' = -(h^2 + t^2)/2 - ln sqrt(2 pi)
+  int form;      // evaluation form taken (kFormDifference or kFormComplement)
 };
 
 enum NbForm : int { kFormDifference = 0, kFormComplement = 1 };
@@ -317,10 +335,16 @@ enum NbForm : int { kFormDifference = 0, kFormComplement = 1 };
 template <bool LO>
 __host__ __device__ inline NBlack normalised_black_t(double x, double s, double bmax) {
   NBlack r;
-  if (!(s > 0.0)) {
-    r.b = 0.0;
-    r.c = bmax;
-    r.bp = (x == 0.0) ? kInvSqrt2Pi : 0.0;
+  if (!(s > 0x1p-1000)) {
+    // s = 0, or so small that x/s would overflow: the limit s -> 0, where b
+    // vanishes faster than any power of s off the money and b ~ s/sqrt(2 pi)
+    // at the money
+    const bool atm = x == 0.0;
+    r.b = atm ? s * kInvSqrt2Pi : 0.0;
+    r.c = bmax - r.b;
+    r.bp = atm ? kInvSqrt2Pi : 0.0;
+    r.ratio = atm ? s : 0.0;
+    r.lnbp = atm ? -kLnSqrt2Pi : -__builtin_inf();
     r.form = kFormDifference;
     return r;
   }
@@ -328,6 +352,7 @@ __host__ __device__ inline NBlack normalised_black_t(double x, double s, double 
   const double ea = -0.5 * fma(h, h, t * t);
   const double E = LO ? fexp_lo(ea) : fexp(ea);
   r.bp = kInvSqrt2Pi * E;
+  r.lnbp = ea - kLnSqrt2Pi;
   const double q1 = -(h + t) * kInvSqrt2, q2 = (t - h) * kInvSqrt2;
   const bool comp = q1 < -coef::kErfcxZ0;
   const double z1 = comp ? -q1 : q1;
@@ -349,12 +374,14 @@ __host__ __device__ inline NBlack normalised_black_t(double x, double s, double 
   if (!comp) {
     constexpr double kSqrtPi = 1.77245385090551602730;
     constexpr double k2BZ = 2.0 * (kB - coef::kErfcxZ0);
-    r.b = r.bp * (kSqrtPi * t * R1 * R2 * fma(-k2BZ * R1, D, B));
+    r.ratio = kSqrtPi * t * R1 * R2 * fma(-k2BZ * R1, D, B);
+    r.b = r.bp * r.ratio;
     r.c = bmax - r.b;
     r.form = kFormDifference;
   } else {
     r.c = 0.5 * E * fma(A, R1, B * R2);
     r.b = bmax - r.c;
+    r.ratio = r.b * (LO ? rcp_lo(r.bp) : rcp(r.bp));
     r.form = kFormComplement;
   }
   return r;

@@ -33,6 +33,8 @@ struct Reduced {
   double F, D, sqrtT;
   double x, beta;  // normalised out-of-the-money call: x <= 0, 0 < beta < e^{x/2}
   double bmax;     // e^{x/2} = min(F, K)/sqrt(F K)
+  double lnb;      // ln beta, to full relative precision also where beta is below
+                   // the normal range (or underflowed) for an out-of-the-money quote
   uint8_t status;
 };
 
@@ -48,7 +50,7 @@ __host__ __device__ inline double forward_of(int model, double fs, double T, dou
 __host__ __device__ inline Reduced reduce_quote(int model, double price, double fs, double K,
                                                 double T, double r, double q, int theta) {
   Reduced o;
-  o.F = 0.0; o.D = 0.0; o.sqrtT = 0.0; o.x = 0.0; o.beta = 0.0; o.bmax = 0.0;
+  o.F = 0.0; o.D = 0.0; o.sqrtT = 0.0; o.x = 0.0; o.beta = 0.0; o.bmax = 0.0; o.lnb = 0.0;
   const bool ok_in = finite_d(price) && finite_d(fs) && finite_d(K) && finite_d(T) &&
                      finite_d(r) && finite_d(q) && fs > 0.0 && K > 0.0 && T > 0.0 &&
                      (theta == 1 || theta == -1);
@@ -79,6 +81,13 @@ __host__ __device__ inline Reduced reduce_quote(int model, double price, double 
   o.bmax = fmin(F, K) * isq;
   // the normalised price can round onto its bound even when Pu < M
   o.status = (o.beta < o.bmax) ? kQOk : kQAboveMax;
+  if (o.beta < 0x1p-1000 && I == 0.0) {
+    // out of the money with a price too small for beta to keep full precision
+    // in binary64: ln beta = ln P + r T - ln(F K)/2 from the price itself
+    o.lnb = flog(price) + r * T - 0.5 * flog(F * K);
+  } else {
+    o.lnb = flog(o.beta);
+  }
   return o;
 }
 

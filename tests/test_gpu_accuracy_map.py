@@ -1,0 +1,44 @@
+"""Dense (x, s) plane: the normalised Black evaluator and both solvers
+against the oracle everywhere the price is solvable (see accuracy_map.py)."""
+import numpy as np
+import pytest
+
+import accuracy_map as AM
+from _helpers import boundary_ambiguous
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_27210_amd as fv
+    fv._native.load()
+    return fv
+
+
+def test_plane_within_bounds(fv):
+    nx = ns = 64
+    xs, ss, res, ok = AM.measure(fv, torch, nx, ns)
+    _, _, x, s = AM.plane(nx, ns)
+    assert ok.sum() > 0.6 * ok.size
+    # b: rounding of h = x/s and of the exp argument, amplified by h^2 + t^2
+    h, t = x / s, 0.5 * s
+    bound = 16.0 * (1.0 + h * h + t * t)
+    eb = res["b"]
+    m = np.isfinite(eb)
+    assert np.all(eb[m] <= bound[m]), (np.max(eb[m] / bound[m]), x[m][np.argmax(eb[m] / bound[m])])
+    for solver in ("lbr", "halley"):
+        r = res[solver + "_ratio"]
+        assert np.nanmax(r) <= 1.0, (solver, np.nanmax(r))
+        mis = res[solver + "_status_mismatch"]
+        if len(mis):
+            K = np.exp(-x[mis])
+            one = np.ones(len(mis))
+            P = AM.oracle.price("black76", one, K, one, 0 * one, 0.0, s[mis],
+                                np.ones(len(mis), dtype=np.int8))
+            amb = boundary_ambiguous("black76", P, one, K, one, 0 * one, 0.0,
+                                     np.ones(len(mis), dtype=np.int8))
+            assert np.all(amb), (solver, x[mis][~amb][:5], s[mis][~amb][:5])
