@@ -35,10 +35,10 @@ if ROOT not in sys.path:
 # The traffic figure is reported only while the kernel sources still hash to
 # ``source_sha256``; the FLOP figure is the algorithmic count of that source.
 LBR_PROFILE = {
-    "source_sha256": "9f553a2c538097f553ad24129d3893949883f130bae25e12f46a9f955049c0a1",
-    "flop_per_quote": 1170.5,
-    "fetch_bytes_per_quote": 49.037,
-    "write_bytes_per_quote": 9.007,
+    "source_sha256": "c00c211462a09224afa231b591d3094bc26395e456b36a3cb591516334039da7",
+    "flop_per_quote": 1149.5,
+    "fetch_bytes_per_quote": 49.036,
+    "write_bytes_per_quote": 9.008,
 }
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
