@@ -154,6 +154,12 @@ def extras(fv, torch, main_inputs):
     n = P.numel()
     ms = _time(torch, lambda: fv.implied_vol("bsm", P, S, K, T, r, flag=flag, q=q, solver="halley"))
     out["halley_wide_bsm"] = {"ms": ms, "implied_vols_per_s": n / ms * 1e3}
+    # the binary32 Halley path on the same quotes rounded to float32
+    f32 = [x.float() for x in (P, S, K, T, r, q)]
+    ms = _time(torch, lambda: fv.implied_vol_f32("bsm", f32[0], f32[1], f32[2], f32[3], f32[4],
+                                                  flag=flag, q=f32[5]))
+    out["halley_f32_wide_bsm"] = {"ms": ms, "implied_vols_per_s": n / ms * 1e3}
+    del f32
     # small batch: launch-latency bound
     wl = W.bs_small()
     a = [d(x) for x in (wl.fs, wl.K, wl.T, wl.r)]

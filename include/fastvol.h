@@ -123,6 +123,34 @@ int fv_price(int model, const fv_quotes *q, fv_arg sigma, double *price_out, voi
 int fv_implied_vol(int model, int solver, const fv_quotes *q, double *sigma_out,
                    uint8_t *status_out, double *const *greeks_out, void *stream);
 
+/* A flat batch in binary32: the layout of fv_quotes with float fields. */
+typedef struct {
+    const float *ptr;  /* device array of n values, or NULL to broadcast `value` */
+    float value;
+} fv_arg_f32;
+
+typedef struct {
+    int64_t n;
+    fv_arg_f32 price, fs, K, T, r, q;
+    const int8_t *flag;
+    int8_t flag_value;
+} fv_quotes_f32;
+
+/* Implied volatility in binary32 arithmetic with the Halley path (paper
+ * section 2.2: the throughput solver for label pipelines that train in
+ * float32): Brenner-Subrahmanyam start, at most 8 Halley steps, bisection
+ * for the quotes that fail the convergence check, all in float.
+ * sigma_out: float [n] (required); status_out: uint8 [n] or NULL.  Statuses
+ * as for fv_implied_vol; FV_Q_NOT_CONVERGED (sigma NaN) also marks a quote
+ * whose normalised out-of-the-money price beta = P_undiscounted/sqrt(F K)
+ * (less the intrinsic value) is below 2^-100, outside this solver's domain
+ * (the binary64 entry points solve it).  Accuracy: |sigma - sigma*| <=
+ * max(4e-6 sigma*, 8 u32 sum_X |d sigma/d X| |X|) against the exact root
+ * sigma* of the given binary32 inputs, u32 = 2^-24 (the second term is the
+ * sensitivity of the root to rounding its inputs). */
+int fv_implied_vol_f32(int model, const fv_quotes_f32 *q, float *sigma_out, uint8_t *status_out,
+                       void *stream);
+
 /* The five Greeks at volatility sigma (paper section 3, get_all_greeks).
  * Each output [n] may be NULL.  q->price is ignored. */
 int fv_greeks(int model, const fv_quotes *q, fv_arg sigma, double *delta, double *gamma,
@@ -235,7 +263,8 @@ enum fv_kernel {
     FV_KERNEL_GREEKS = 3,
     FV_KERNEL_BACKWARD = 4,
     FV_KERNEL_CHAINS = 5,
-    FV_KERNEL_COUNT = 6
+    FV_KERNEL_IV_HALLEY_F32 = 6,
+    FV_KERNEL_COUNT = 7
 };
 int fv_set_launch(int kernel, int block, int quotes_per_thread);
 int fv_get_launch(int kernel, int *block, int *quotes_per_thread);

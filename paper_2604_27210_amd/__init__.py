@@ -9,14 +9,14 @@ The native library is loaded lazily, on the first call that needs it.
 """
 from . import _native  # noqa: F401
 
-__all__ = ["price", "implied_vol", "greeks", "implied_vol_backward", "implied_vol_chains",
+__all__ = ["price", "implied_vol", "implied_vol_f32", "greeks", "implied_vol_backward", "implied_vol_chains",
            "price_backward", "price_autograd", "lbr_trace",
            "normalised_black", "set_launch", "get_launch", "autotune", "version",
            "IVFunction", "implied_vol_autograd"]
 
 
 def __getattr__(name):
-    if name in ("price", "implied_vol", "greeks", "implied_vol_backward", "implied_vol_chains",
+    if name in ("price", "implied_vol", "implied_vol_f32", "greeks", "implied_vol_backward", "implied_vol_chains",
                 "normalised_black", "set_launch", "get_launch", "autotune", "version",
                 "price_backward", "lbr_trace"):
         from . import api

@@ -23,7 +23,8 @@ FV_E_UNSUPPORTED = -3
 MODELS = {"black76": 0, "black": 0, "b76": 0, "bs": 1, "black_scholes": 1, "bsm": 2,
           "black_scholes_merton": 2}
 SOLVERS = {"lbr": 0, "jackel": 0, "halley": 1}
-KERNELS = {"price": 0, "iv_lbr": 1, "iv_halley": 2, "greeks": 3, "backward": 4, "chains": 5}
+KERNELS = {"price": 0, "iv_lbr": 1, "iv_halley": 2, "greeks": 3, "backward": 4, "chains": 5,
+           "iv_halley_f32": 6}
 
 # per-quote status codes
 Q_OK, Q_AT_INTRINSIC, Q_BELOW_INTRINSIC, Q_ABOVE_MAX, Q_INVALID_INPUT, Q_NOT_CONVERGED = range(6)
@@ -40,6 +41,17 @@ class FvQuotes(ctypes.Structure):
                 ("flag", ctypes.c_void_p), ("flag_value", ctypes.c_int8)]
 
 
+class FvArgF32(ctypes.Structure):
+    _fields_ = [("ptr", ctypes.c_void_p), ("value", ctypes.c_float)]
+
+
+class FvQuotesF32(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64),
+                ("price", FvArgF32), ("fs", FvArgF32), ("K", FvArgF32), ("T", FvArgF32),
+                ("r", FvArgF32), ("q", FvArgF32),
+                ("flag", ctypes.c_void_p), ("flag_value", ctypes.c_int8)]
+
+
 class FvChains(ctypes.Structure):
     _fields_ = [("n_chains", ctypes.c_int64), ("n_maturities", ctypes.c_int64),
                 ("n_quotes", ctypes.c_int64),
@@ -53,7 +65,7 @@ class FvSviProblem(ctypes.Structure):
                 ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double)]
 
 
-EXPORTS = ["fv_price", "fv_implied_vol", "fv_greeks", "fv_implied_vol_backward", "fv_price_backward",
+EXPORTS = ["fv_price", "fv_implied_vol", "fv_implied_vol_f32", "fv_greeks", "fv_implied_vol_backward", "fv_price_backward",
            "fv_implied_vol_chains", "fv_normalised_black", "fv_lbr_trace", "fv_set_launch", "fv_get_launch",
            "fv_autotune", "fv_svi_adam_step", "fv_svi_vols", "fv_last_error", "fv_version"]
 
@@ -78,6 +90,7 @@ def load():
     P, I, I64, D, V = ctypes.POINTER, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
     lib.fv_price.argtypes = [I, P(FvQuotes), FvArg, V, V]
     lib.fv_implied_vol.argtypes = [I, I, P(FvQuotes), V, V, V, V]
+    lib.fv_implied_vol_f32.argtypes = [I, P(FvQuotesF32), V, V, V]
     lib.fv_greeks.argtypes = [I, P(FvQuotes), FvArg, V, V, V, V, V, V]
     lib.fv_implied_vol_backward.argtypes = [I, P(FvQuotes), V, V, V, V, V, V, V, V, V]
     lib.fv_price_backward.argtypes = [I, P(FvQuotes), FvArg, V, V, V, V, V, V, V, V]

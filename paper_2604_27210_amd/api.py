@@ -44,6 +44,24 @@ def _dev_tensor(t: torch.Tensor, name: str, dtype=torch.float64) -> torch.Tensor
     return t
 
 
+def _flag_arg(flag, n, keep):
+    """(pointer, broadcast value) of a flag argument: 'c'/'p', +1/-1, or an
+    int8 GPU tensor of n entries (kept alive in `keep`)."""
+    if isinstance(flag, str):
+        return None, (1 if flag.lower().startswith("c") else -1)
+    if isinstance(flag, (int, float)):
+        return None, int(flag)
+    if isinstance(flag, torch.Tensor) and flag.dim() > 0:
+        if flag.dtype != torch.int8:
+            raise TypeError("flag tensor must be int8 (+1 call / -1 put)")
+        _dev_tensor(flag, "flag", torch.int8)
+        if flag.numel() != n:
+            raise ValueError("flag length mismatch")
+        keep.append(flag)
+        return ctypes.c_void_p(flag.data_ptr()), 1
+    raise TypeError("flag must be 'c'/'p', +1/-1 or an int8 GPU tensor")
+
+
 class _Batch:
     """Collects the per-quote fields of one call, resolves n and the device,
     and keeps the tensors alive for the duration of the launch."""
@@ -77,20 +95,7 @@ class _Batch:
 
     def flag(self, flag):
         """Returns (pointer, broadcast value)."""
-        if isinstance(flag, str):
-            return None, (1 if flag.lower().startswith("c") else -1)
-        if isinstance(flag, (int, float)):
-            return None, int(flag)
-        if isinstance(flag, torch.Tensor) and flag.dim() > 0:
-            f = flag
-            if f.dtype != torch.int8:
-                raise TypeError("flag tensor must be int8 (+1 call / -1 put)")
-            _dev_tensor(f, "flag", torch.int8)
-            if f.numel() != self.n:
-                raise ValueError("flag length mismatch")
-            self.keep.append(f)
-            return ctypes.c_void_p(f.data_ptr()), 1
-        raise TypeError("flag must be 'c'/'p', +1/-1 or an int8 GPU tensor")
+        return _flag_arg(flag, self.n, self.keep)
 
     def quotes(self, price=None, fs=None, K=None, T=None, r=None, q=None, flag=1) -> N.FvQuotes:
         fp, fv = self.flag(flag)
@@ -139,6 +144,42 @@ def implied_vol(model, price, fs, K, T, r, flag="c", q=None, solver="lbr", greek
     if greeks:
         res.append(gk)
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def implied_vol_f32(model, price, fs, K, T, r, flag="c", q=None, with_status=True, stream=None):
+    """Implied volatility in binary32 arithmetic (Halley path): per-quote
+    fields are Python floats or contiguous float32 GPU tensors; returns a
+    float32 sigma (and the uint8 status with ``with_status``)."""
+    fields = dict(price=price, fs=fs, K=K, T=T, r=r, q=q)
+    n, device, keep = None, None, []
+    for name, v in fields.items():
+        if isinstance(v, torch.Tensor) and v.dim() > 0:
+            _dev_tensor(v, name, torch.float32)
+            if v.dim() != 1:
+                raise ValueError("%s must be 1-D" % name)
+            if n is None:
+                n, device = v.numel(), v.device
+            elif v.numel() != n:
+                raise ValueError("length mismatch: %s has %d, expected %d" % (name, v.numel(), n))
+    if n is None:
+        raise ValueError("at least one per-quote field must be a 1-D GPU tensor")
+
+    def arg(v, name):
+        if v is None:
+            return N.FvArgF32(None, 0.0)
+        if isinstance(v, torch.Tensor) and v.dim() > 0:
+            keep.append(v)
+            return N.FvArgF32(ctypes.c_void_p(v.data_ptr()), 0.0)
+        return N.FvArgF32(None, float(v))
+
+    fp, fv = _flag_arg(flag, n, keep)
+    qs = N.FvQuotesF32(n, arg(price, "price"), arg(fs, "fs"), arg(K, "K"), arg(T, "T"),
+                       arg(r, "r"), arg(q if q is not None else 0.0, "q"), fp, fv)
+    sig = torch.empty(n, dtype=torch.float32, device=device)
+    st = torch.empty(n, dtype=torch.uint8, device=device) if with_status else None
+    N.check(N.load().fv_implied_vol_f32(_model(model), ctypes.byref(qs), _ptr(sig), _ptr(st),
+                                        ctypes.c_void_p(_stream_ptr(stream))), "fv_implied_vol_f32")
+    return (sig, st) if with_status else sig
 
 
 def greeks(model, fs, K, T, r, sigma, flag="c", q=None, stream=None) -> dict:

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "../../include/fastvol.h"
+#include "fv_f32.h"
 #include "fv_host.h"
 #include "fv_quote.h"
 
@@ -277,6 +278,89 @@ __attribute__((amdgpu_waves_per_eu(FV_WAVES(GREEKS)))) void k_iv_halley(KQuotes 
 }
 
 // ------------------------------------------------------------- Greeks
+// ------------------------------------------------------------- IV: Halley, binary32
+struct KQuotes32 {
+  int64_t n;
+  fv_arg_f32 price, fs, K, T, r, q;
+  const int8_t* flag;
+  int8_t flag_value;
+};
+
+__device__ __forceinline__ float ld32(const fv_arg_f32& a, int64_t i) {
+  return a.ptr ? a.ptr[i] : a.value;
+}
+
+struct Pending32 {
+  int64_t i;
+  float lo, hi;
+};
+
+// The binary32 twin of k_iv_halley: same per-lane Halley, same ballot + LDS
+// compaction of the lanes that fail the convergence check and bisection over
+// the packed queue, in float arithmetic throughout.
+template <int MODEL>
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_iv_halley32(
+    KQuotes32 q, float* __restrict__ sig_out, uint8_t* __restrict__ st_out, int qpt) {
+  extern __shared__ unsigned char smem_raw[];
+  Pending32* queue = reinterpret_cast<Pending32*>(smem_raw);
+  __shared__ int qcount;
+  if (threadIdx.x == 0) qcount = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x * qpt + threadIdx.x;
+  for (int k = 0; k < qpt; ++k) {
+    const int64_t i = base + (int64_t)k * blockDim.x;
+    bool fail = false;
+    fv32::HalleyState hs;
+    hs.lo = 0.0f;
+    hs.hi = 0.0f;
+    if (i < q.n) {
+      const float P = ld32(q.price, i), fs = ld32(q.fs, i), K = ld32(q.K, i),
+                  T = ld32(q.T, i), r = ld32(q.r, i);
+      const float qy = MODEL == fv::kBlackScholesMerton ? ld32(q.q, i) : 0.0f;
+      const int th = q.flag ? (int)q.flag[i] : (int)q.flag_value;
+      const fv32::Reduced rd = fv32::reduce_quote(MODEL, P, fs, K, T, r, qy, th);
+      const uint8_t st = rd.status;
+      float sg = st == fv::kQAtIntrinsic ? 0.0f : __builtin_nanf("");
+      if (st == fv::kQOk) {
+        hs = fv32::halley_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kHalleySteps);
+        sg = hs.s / rd.sqrtT;
+        fail = !hs.converged;
+      }
+      if (!fail) {
+        sig_out[i] = sg;
+        if (st_out) st_out[i] = st;
+      }
+    }
+    const uint64_t mask = __ballot(fail);
+    if (mask) {
+      int wbase = 0;
+      const int cnt = __popcll(mask);
+      const unsigned first = __ffsll((unsigned long long)mask) - 1;
+      if (__lane_id() == first) wbase = atomicAdd(&qcount, cnt);
+      wbase = __shfl(wbase, first);
+      if (fail) {
+        const int slot = wbase + __popcll(mask & lanemask_lt());
+        queue[slot].i = i;
+        queue[slot].lo = hs.lo;
+        queue[slot].hi = hs.hi;
+      }
+    }
+  }
+  __syncthreads();
+  const int m = qcount;
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    const int64_t i = queue[j].i;
+    const float P = ld32(q.price, i), fs = ld32(q.fs, i), K = ld32(q.K, i), T = ld32(q.T, i),
+                r = ld32(q.r, i);
+    const float qy = MODEL == fv::kBlackScholesMerton ? ld32(q.q, i) : 0.0f;
+    const int th = q.flag ? (int)q.flag[i] : (int)q.flag_value;
+    const fv32::Reduced rd = fv32::reduce_quote(MODEL, P, fs, K, T, r, qy, th);
+    const float s = fv32::bisection_solve(rd.x, rd.beta, rd.bmax, queue[j].lo, queue[j].hi, 2e-7f);
+    sig_out[i] = s / rd.sqrtT;
+    if (st_out) st_out[i] = fv::kQOk;
+  }
+}
+
 template <int MODEL>
 __global__ __launch_bounds__(kMaxBlock) void k_greeks(KQuotes q, fv_arg sigma, GreekOut g, int qpt) {
   const int64_t base = (int64_t)blockIdx.x * blockDim.x * qpt + threadIdx.x;
@@ -530,6 +614,22 @@ __global__ void k_normalised_black(int64_t n, const double* __restrict__ x,
   out[i] = b;
 }
 
+// binary32 copies of the autotuner's quotes (price, S, K, T, r, q, in that
+// order, n floats each)
+__global__ void k_tune_to_f32(int64_t n, const double* __restrict__ P, const double* __restrict__ S,
+                              const double* __restrict__ K, const double* __restrict__ T,
+                              const double* __restrict__ r, const double* __restrict__ q,
+                              float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = (float)P[i];
+  out[n + i] = (float)S[i];
+  out[2 * n + i] = (float)K[i];
+  out[3 * n + i] = (float)T[i];
+  out[4 * n + i] = (float)r[i];
+  out[5 * n + i] = (float)q[i];
+}
+
 // ------------------------------------------------------------- autotune inputs
 // Synthetic in-range quotes for timing candidate launch shapes: a
 // counter-based generator (the splitmix64 output function of Steele, Lea &
@@ -607,6 +707,7 @@ LaunchShape g_shape[FV_KERNEL_COUNT] = {
     {256, 1},  // Greeks
     {256, 1},  // backward
     {256, 8},  // chains
+    {128, 4},  // IV Halley, binary32
 };
 
 bool valid_shape(int block, int qpt) {
@@ -756,6 +857,38 @@ int fv_implied_vol(int model, int solver, const fv_quotes* q, double* sigma_out,
   }
 #undef FV_HAL
   return launched("fv_implied_vol(Halley)");
+}
+
+int fv_implied_vol_f32(int model, const fv_quotes_f32* q, float* sigma_out,
+                       uint8_t* status_out, void* stream) {
+  if (model < FV_MODEL_BLACK76 || model > FV_MODEL_BSM)
+    return fail(FV_E_INVALID_ARG, "model out of range");
+  if (!q) return fail(FV_E_INVALID_ARG, "quotes pointer is NULL");
+  if (q->n < 0) return fail(FV_E_INVALID_ARG, "n < 0");
+  if (!q->flag && q->flag_value != 1 && q->flag_value != -1)
+    return fail(FV_E_INVALID_ARG, "broadcast flag_value must be +1 or -1");
+  if (q->n == 0) return FV_OK;
+  if (!sigma_out) return fail(FV_E_INVALID_ARG, "sigma_out is NULL");
+  KQuotes32 k;
+  k.n = q->n;
+  k.price = q->price;
+  k.fs = q->fs;
+  k.K = q->K;
+  k.T = q->T;
+  k.r = q->r;
+  k.q = q->q;
+  k.flag = q->flag;
+  k.flag_value = q->flag_value;
+  const LaunchShape sh = shape_for(FV_KERNEL_IV_HALLEY_F32, q->n);
+  const dim3 grid = grid_for(q->n, sh), block(sh.block);
+  const size_t lds = sizeof(Pending32) * (size_t)sh.block * sh.qpt;
+  hipStream_t s = (hipStream_t)stream;
+  switch (model) {
+    case FV_MODEL_BLACK76: k_iv_halley32<0><<<grid, block, lds, s>>>(k, sigma_out, status_out, sh.qpt); break;
+    case FV_MODEL_BLACK_SCHOLES: k_iv_halley32<1><<<grid, block, lds, s>>>(k, sigma_out, status_out, sh.qpt); break;
+    default: k_iv_halley32<2><<<grid, block, lds, s>>>(k, sigma_out, status_out, sh.qpt); break;
+  }
+  return launched("fv_implied_vol_f32");
 }
 
 int fv_greeks(int model, const fv_quotes* q, fv_arg sigma, double* delta, double* gamma,
@@ -919,6 +1052,7 @@ int fv_autotune(int kernel, int model, int64_t n_hint, void* stream) {
          *P = (double*)alloc(n * 8), *o1 = (double*)alloc(n * 8), *o2 = (double*)alloc(n * 8);
   int8_t* flag = (int8_t*)alloc(n);
   uint8_t* st = (uint8_t*)alloc(n);
+  float* f32 = kernel == FV_KERNEL_IV_HALLEY_F32 ? (float*)alloc((size_t)6 * n * 4) : nullptr;
   int64_t *cmo = (int64_t*)alloc((n_chains + 1) * 8), *mqo = (int64_t*)alloc((n_mat + 1) * 8);
   double *cF = (double*)alloc(n_chains * 8), *cr = (double*)alloc(n_chains * 8),
          *cT = (double*)alloc(n_mat * 8);
@@ -981,6 +1115,19 @@ int fv_autotune(int kernel, int model, int64_t n_hint, void* stream) {
     rc = fv_price(model, &qs, sa, P, stream);
   }
   g_shape[FV_KERNEL_PRICE] = saved_price;
+  fv_quotes_f32 q32;
+  memset(&q32, 0, sizeof(q32));
+  if (f32) {
+    k_tune_to_f32<<<g256, 256, 0, s>>>(n, P, S, K, T, r, q, f32);
+    q32.n = n;
+    q32.price.ptr = f32;
+    q32.fs.ptr = f32 + n;
+    q32.K.ptr = f32 + 2 * n;
+    q32.T.ptr = f32 + 3 * n;
+    q32.r.ptr = f32 + 4 * n;
+    q32.q.ptr = f32 + 5 * n;
+    q32.flag = flag;
+  }
 
   auto run = [&]() -> int {
     switch (kernel) {
@@ -992,6 +1139,8 @@ int fv_autotune(int kernel, int model, int64_t n_hint, void* stream) {
       case FV_KERNEL_BACKWARD:
         return fv_implied_vol_backward(model, &qs, sig, sig, o1, o2, nullptr, nullptr, nullptr,
                                        nullptr, stream);
+      case FV_KERNEL_IV_HALLEY_F32:
+        return fv_implied_vol_f32(model, &q32, (float*)o1, st, stream);
       default: return fv_implied_vol_chains(FV_SOLVER_LBR, &cs, o1, st, stream);
     }
   };

@@ -23,7 +23,9 @@ definitions evaluated in mpmath (no coefficients are taken from any library):
    A second, lower-degree fit of the same form (``kErfcxLo``, relative error
    ~1e-8) serves the initial guess of the implied-volatility iteration,
    which only has to land within ~1e-3 of the root for two quartically
-   convergent steps to reach binary64 precision.
+   convergent steps to reach binary64 precision.  A third
+   (``kErfcxF32``, degree 13, value ~6e-10 and derivative ~2.4e-7 relative)
+   serves the binary32 solver, where binary32 rounding dominates both.
 
 2. The inverse standard normal CDF on (0, 1/2] (initial guess only), as one
    rational function in the tail variable r = sqrt(-2 ln p) of the ratio
@@ -44,6 +46,8 @@ ERFCX_B = mp.mpf("4.25")
 ERFCX_DEG = 25
 ERFCX_LO_B = mp.mpf("3.5")
 ERFCX_LO_DEG = 12
+ERFCX_F32_B = mp.mpf("3.5")
+ERFCX_F32_DEG = 13
 PHI_INV_DEG = (9, 9)
 P_MIN = mp.mpf("1e-310")
 
@@ -164,6 +168,8 @@ def main():
     eval_err, deriv_err = check_erfcx(ec, ERFCX_B)
     el = fit_erfcx(ERFCX_LO_B, ERFCX_LO_DEG)
     lo_err, lo_deriv = check_erfcx(el, ERFCX_LO_B)
+    e32 = fit_erfcx(ERFCX_F32_B, ERFCX_F32_DEG)
+    f32_err, f32_deriv = check_erfcx(e32, ERFCX_F32_B)
     pP, pQ, perr = fit_phi_inv()
     n3 = lambda v: mp.nstr(v, 3)
     out = [
@@ -172,6 +178,8 @@ def main():
         "// erfcx fit max rel err %s, derivative max rel err %s\n" % (n3(eval_err), n3(deriv_err)),
         "// guess-precision erfcx (same form, B = kErfcxLoB): max rel err %s, derivative %s\n"
         % (n3(lo_err), n3(lo_deriv)),
+        "// binary32 erfcx (same form, B = kErfcxF32B): max rel err %s, derivative %s\n"
+        % (n3(f32_err), n3(f32_deriv)),
         "// Inverse normal CDF on (0, 1/2]: Phi^{-1}(p) = (p - 1/2) P(r)/Q(r),\n",
         "// r = sqrt(-2 ln p); max rel err %s\n" % n3(perr),
         "#pragma once\n\nnamespace fv {\nnamespace coef {\n\n",
@@ -180,6 +188,8 @@ def main():
         _arr("kErfcx", ec),
         "\nconstexpr double kErfcxLoB = %s;\n" % mp.nstr(ERFCX_LO_B, 20),
         _arr("kErfcxLo", el),
+        "\nconstexpr double kErfcxF32B = %s;\n" % mp.nstr(ERFCX_F32_B, 20),
+        _arr("kErfcxF32", e32),
         "\n",
         _arr("kPhiInvP", pP),
         _arr("kPhiInvQ", pQ),

@@ -66,18 +66,21 @@ def iv_tolerance(solver, sigma_ref, cabs):
     return np.maximum(base, 8 * U * cabs)
 
 
-def boundary_ambiguous(model, P, fs, K, T, r, q, flag, ulps=16):
+def boundary_ambiguous(model, P, fs, K, T, r, q, flag, ulps=16, u=None):
     """Quotes whose undiscounted price lies within a few ulps of the
     intrinsic value or of the upper bound: their status is decided by the
     last bit of a forward or discount factor, so two correct binary64
-    implementations may disagree."""
+    implementations may disagree.  `u` is the unit roundoff of the
+    arithmetic deciding the status (binary64 by default; 2^-24 for the
+    binary32 solver)."""
+    u = U if u is None else u
     F, D = forward_discount(model, fs, T, r, q)
     Pu = P / D
     call = np.asarray(flag) > 0
     intrinsic = np.where(call, np.maximum(F - K, 0.0), np.maximum(K - F, 0.0))
     upper = np.where(call, F, K)
     scale = np.maximum(np.abs(Pu), np.maximum(np.abs(F), np.abs(K)))
-    near = (np.abs(Pu - intrinsic) <= ulps * U * scale) | (np.abs(upper - Pu) <= ulps * U * scale)
+    near = (np.abs(Pu - intrinsic) <= ulps * u * scale) | (np.abs(upper - Pu) <= ulps * u * scale)
     return near
 
 
