@@ -114,11 +114,10 @@ __host__ __device__ inline NBlack normalised_black(float x, float s, float bmax)
   const float z1 = comp ? -q1 : q1;
   const float R1 = rcp(z1 + kB), R2 = rcp(q2 + kB);
   const float y1 = (z1 - kShift) * R1, y2 = (q2 - kShift) * R2;
-  float A = (float)fv::coef::kErfcxF32[kDeg], B = A, D = 0.0f;
+  float B = (float)fv::coef::kErfcxF32[kDeg], D = 0.0f;
 #pragma unroll
   for (int i = kDeg - 1; i >= 0; --i) {
     D = fmaf(D, y1, B);
-    A = fmaf(A, y1, (float)fv::coef::kErfcxF32[i]);
     B = fmaf(B, y2, (float)fv::coef::kErfcxF32[i]);
   }
   if (!comp) {
@@ -126,6 +125,7 @@ __host__ __device__ inline NBlack normalised_black(float x, float s, float bmax)
     r.b = r.bp * (kSqrtPi * t * R1 * R2 * fmaf(-k2BZ * R1, D, B));
     r.c = bmax - r.b;
   } else {
+    const float A = fmaf(y1 - y2, D, B);  // p(y1); both terms >= 0
     r.c = 0.5f * E * fmaf(A, R1, B * R2);
     r.b = bmax - r.c;
   }

@@ -311,7 +311,8 @@ __host__ __device__ inline double inv_norm_cdf_lower(double p) {
 //    any t (this replaces a small-t Taylor branch) and any h (this replaces
 //    an asymptotic deep-wing branch).
 //  * complement form (q1 < -Z0, i.e. h + t > Z0 sqrt2): b_max - b from the
-//    sum above, with erfcx(-q1) from the same recurrence, then
+//    sum above, with erfcx(-q1) = p(y1) R1 from the same recurrences as
+//    p(y1) = p(y2) + (y1 - y2) D, then
 //    b = b_max - (b_max - b).  Here b >= 0.3 b_max, so the subtraction
 //    loses at most two bits, and the upper objective gets b_max - b
 //    without cancellation.
@@ -363,12 +364,11 @@ __host__ __device__ inline NBlack normalised_black_t(double x, double s, double 
   const double R1 = LO ? rcp_lo(z1 + kB) : rcp(z1 + kB);
   const double R2 = LO ? rcp_lo(q2 + kB) : rcp(q2 + kB);
   const double y1 = (z1 - kShift) * R1, y2 = (q2 - kShift) * R2;
-  // A = p(y1), B = p(y2), D = (p(y1) - p(y2))/(y1 - y2)
-  double A = kC[kDeg], B = A, D = 0.0;
+  // B = p(y2), D = (p(y1) - p(y2))/(y1 - y2) by two Horner recurrences
+  double B = kC[kDeg], D = 0.0;
 #pragma unroll
   for (int i = kDeg - 1; i >= 0; --i) {
     D = fma(D, y1, B);
-    A = fma(A, y1, kC[i]);
     B = fma(B, y2, kC[i]);
   }
   if (!comp) {
@@ -379,6 +379,9 @@ __host__ __device__ inline NBlack normalised_black_t(double x, double s, double 
     r.c = bmax - r.b;
     r.form = kFormDifference;
   } else {
+    // p(y1) = p(y2) + (y1 - y2) D: y1 <= y2 and D <= 0, so both terms are
+    // non-negative
+    const double A = fma(y1 - y2, D, B);
     r.c = 0.5 * E * fma(A, R1, B * R2);
     r.b = bmax - r.c;
     r.ratio = r.b * (LO ? rcp_lo(r.bp) : rcp(r.bp));
