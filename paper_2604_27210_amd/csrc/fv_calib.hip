@@ -74,12 +74,31 @@ __device__ __forceinline__ double svi_w(const SviMat& q, double k) {
   return q.a + q.b * (q.rho * dk + sqrt(dk * dk + q.s2));
 }
 
+// sqrt((k - m)^2 + s^2) and its reciprocal, shared by w and dw/dtheta; the
+// refined hardware reciprocal square root where the radicand is a normal
+// number, the library square root otherwise (s underflowed to 0 at k = m)
+struct SviRoot {
+  double dk, rt, irt;
+};
+
+__device__ __forceinline__ SviRoot svi_root(const SviMat& q, double k) {
+  SviRoot o;
+  o.dk = k - q.m;
+  const double u = fma(o.dk, o.dk, q.s2);
+  if (u >= 2.2250738585072014e-308) {
+    o.irt = fv::rsqrt(u);
+    o.rt = u * o.irt;
+  } else {
+    o.rt = sqrt(u);
+    o.irt = 1.0 / o.rt;
+  }
+  return o;
+}
+
 // g_w * dw/dtheta added into acc[0..4]
-__device__ __forceinline__ void svi_add_grad(const SviMat& q, double k, double g_w,
+__device__ __forceinline__ void svi_add_grad(const SviMat& q, const SviRoot& g, double g_w,
                                              double* acc) {
-  const double dk = k - q.m;
-  const double rt = sqrt(dk * dk + q.s2);
-  const double irt = 1.0 / rt;
+  const double dk = g.dk, rt = g.rt, irt = g.irt;
   acc[0] += g_w;
   acc[1] += g_w * (q.rho * dk + rt) * q.sb;
   acc[2] += g_w * q.b * dk * (1.0 - q.rho * q.rho);
@@ -97,7 +116,7 @@ __device__ __forceinline__ int64_t chain_of(const int64_t* off, int64_t n_chains
   return lo;
 }
 
-__global__ __launch_bounds__(kCalibBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_svi_grad(
+__global__ __launch_bounds__(kCalibBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_svi_grad(
     KSvi c, const double* __restrict__ theta,
                                                           double* __restrict__ grad,
                                                           double* __restrict__ loss_parts,
@@ -106,7 +125,7 @@ __global__ __launch_bounds__(kCalibBlock) __attribute__((amdgpu_waves_per_eu(3))
   const int64_t m = blockIdx.x;
   const int64_t ch = chain_of(c.chain_mat_off, c.n_chains, m);
   const double F = c.F[ch], T = c.T[m];
-  const double sqT = sqrt(T), iT = 1.0 / T;
+  const double sqT = sqrt(T), iT = 1.0 / T, isqT = 1.0 / sqT;
   double th[5];
 #pragma unroll
   for (int j = 0; j < 5; ++j) th[j] = theta[m * 5 + j];
@@ -116,14 +135,16 @@ __global__ __launch_bounds__(kCalibBlock) __attribute__((amdgpu_waves_per_eu(3))
   for (int64_t i = c.mat_quote_off[m] + threadIdx.x; i < c.mat_quote_off[m + 1];
        i += blockDim.x) {
     const double tgt = c.iv_target[i];
-    const double lfk = log(F / c.K[i]);  // ln(F/K) = -k
-    const double w = svi_w(q, -lfk);
+    const double lfk = fv::flog(F * fv::rcp(c.K[i]));  // ln(F/K) = -k
+    const SviRoot g = svi_root(q, -lfk);
+    const double w = fma(q.b, fma(q.rho, g.dk, g.rt), q.a);
     if (!(w > kWMin) || !fv::finite_d(tgt)) continue;
-    const double sigma = sqrt(w * iT);
+    const double v = w * iT;
+    const double sigma = v * fv::rsqrt(v);
     const double s1 = sigma * sqT;
     // out-of-the-money side: x <= 0, beta = b(x, s1)
     const double x = -fabs(lfk);
-    const double bmax = exp(0.5 * x);
+    const double bmax = fv::fexp(0.5 * x);
     const fv::NBlack nb = fv::normalised_black(x, s1, bmax);
     // IV(P(sigma)) through the LBR solver; where the model price is not
     // solvable in binary64 (b rounded onto 0 or onto its bound b_max) the
@@ -134,15 +155,15 @@ __global__ __launch_bounds__(kCalibBlock) __attribute__((amdgpu_waves_per_eu(3))
       // b is below the normal range)
       const double ln_beta = nb.lnbp + fv::flog(nb.ratio);
       const fv::LbrResult res = fv::lbr_solve(x, nb.b, bmax, ln_beta, 2, 4, 1e-6);
-      iv = res.s / sqT;
+      iv = res.s * isqT;
       // vega(v) = D F phi(d1(v)) sqrt(T); only vega(sigma)/vega(iv) enters
       const double s2 = res.s;
-      const double d1a = lfk / s1 + 0.5 * s1, d1b = lfk / s2 + 0.5 * s2;
-      ratio = exp(-0.5 * (d1a * d1a - d1b * d1b));
+      const double d1a = fma(lfk, fv::rcp(s1), 0.5 * s1), d1b = fma(lfk, fv::rcp(s2), 0.5 * s2);
+      ratio = fv::fexp(-0.5 * (d1a - d1b) * (d1a + d1b));
     }
     const double e = iv - tgt;
-    const double g_w = e * inv_n * ratio / (sigma * T);  // (2 e/N) ratio / (2 sigma T)
-    svi_add_grad(q, -lfk, g_w, acc);
+    const double g_w = e * inv_n * ratio * fv::rcp(sigma * T);  // (2 e/N) ratio / (2 sigma T)
+    svi_add_grad(q, g, g_w, acc);
     acc[5] += e * e;
   }
 #pragma unroll
