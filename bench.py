@@ -140,6 +140,40 @@ def _time(torch, fn, reps=10, warm=2):
     return float(np.median(ts))
 
 
+def _time_cold(torch, fn, reps=10, warm=2):
+    """As _time, with the caches flushed before every timed call by a
+    1 GiB device write (larger than L2 plus the 256 MB Infinity Cache)."""
+    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    for _ in range(warm):
+        fn()
+    ts = []
+    for _ in range(reps):
+        flush.fill_(1.0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del flush
+    return float(np.median(ts))
+
+
+def _graph_replay_us(torch, fn, reps=50):
+    """Median time (us) of one replay of a graph that captured fn once."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()  # warm-up on the side stream, outside the capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    return _time(torch, g.replay, reps=reps, warm=3) * 1e3
+
+
 def extras(fv, torch, main_inputs):
     """Secondary measurements beside the headline: the Halley path on the
     same batch, the small batch's latency, ragged chains (one persistent
@@ -166,8 +200,9 @@ def extras(fv, torch, main_inputs):
     fl = d(wl.flag, torch.int8)
     Ps = fv.price("bs", a[0], a[1], a[2], a[3], d(wl.sigma_true), flag=fl)
     for solver in ("lbr", "halley"):
-        ms = _time(torch, lambda: fv.implied_vol("bs", Ps, *a, flag=fl, solver=solver), reps=50)
-        out["bs_4096_%s_us_per_call" % solver] = ms * 1e3
+        call = lambda: fv.implied_vol("bs", Ps, *a, flag=fl, solver=solver)
+        out["bs_4096_%s_us_per_call" % solver] = _time(torch, call, reps=50) * 1e3
+        out["bs_4096_%s_us_per_graph_replay" % solver] = _graph_replay_us(torch, call)
     # ragged chains
     ch = W.b76_chains()
     flat = ch.flatten()
@@ -175,7 +210,9 @@ def extras(fv, torch, main_inputs):
     F, rc, Tm, Kq, flq = d(ch.F), d(ch.r), d(ch.T), d(ch.K), d(ch.flag, torch.int8)
     fF, fT, fr = d(flat.fs), d(flat.T), d(flat.r)
     Pc = fv.price("black76", fF, Kq, fT, fr, d(ch.sigma_true), flag=flq)
-    ms_p = _time(torch, lambda: fv.implied_vol_chains(cd["cmo"], cd["mqo"], F, rc, Tm, Pc, Kq, flq))
+    persistent = lambda: fv.implied_vol_chains(cd["cmo"], cd["mqo"], F, rc, Tm, Pc, Kq, flq)
+    ms_p = _time(torch, persistent)
+    ms_pc = _time_cold(torch, persistent)
     ms_f = _time(torch, lambda: fv.implied_vol("black76", Pc, fF, Kq, fT, fr, flag=flq))
     off = ch.mat_quote_off[ch.chain_mat_off]
 
@@ -186,7 +223,8 @@ def extras(fv, torch, main_inputs):
                            flag=flq[lo:hi])
     ms_c = _time(torch, per_chain, reps=3, warm=1)
     out["ragged_b76_chains"] = {"n_quotes": ch.n, "n_chains": ch.n_chains, "n_maturities": ch.n_mat,
-                                "persistent_ms": ms_p, "flat_expanded_ms": ms_f,
+                                "persistent_ms": ms_p, "persistent_cold_ms": ms_pc,
+                                "flat_expanded_ms": ms_f,
                                 "per_chain_launches_ms": ms_c,
                                 "persistent_implied_vols_per_s": ch.n / ms_p * 1e3}
     # forward + backward (differentiable IV), 1M quotes
