@@ -248,10 +248,11 @@ int fv_lbr_trace(int model, const fv_quotes *q, uint32_t *path_out, void *stream
  * overrides the launch shape of one kernel family (FV_KERNEL_*); block must
  * be a multiple of 64 in [64, 512] and quotes_per_thread in [1, 16].
  * fv_get_launch reads the current shape.  The shape applies as set to
- * batches large enough to fill the device; a batch with fewer than two
- * workgroups per compute unit runs with fewer quotes per thread (halved
- * until it has two, or one per thread), and with fewer than one workgroup
- * per compute unit also with 64-thread workgroups.  No result depends on the
+ * batches large enough to fill the device; a batch that would give fewer
+ * than 8 waves per SIMD (32 per compute unit) runs with fewer quotes per
+ * thread (halved until it has them, or one per thread), and with fewer than
+ * one workgroup per compute unit also with 64-thread workgroups.  No result
+ * depends on the
  * shape.  fv_autotune times the candidate shapes (block 64..512, 1..8 quotes
  * per thread) of one kernel family on the given stream with synthetic
  * in-range quotes of size n_hint (the library allocates and frees scratch

@@ -106,8 +106,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_price(KQuotes q, fv_arg sigma, do
         fv::finite_d(qy) && fv::finite_d(sg) && fs > 0.0 && K > 0.0 && T > 0.0 &&
         sg >= 0.0 && (th == 1 || th == -1)) {
       const double F = fv::forward_of(MODEL, fs, T, r, qy);
-      const double D = exp(-r * T);
-      p = fv::price_at(F, K, D, sg, sqrt(T), th);
+      const double D = fv::fexp(-r * T);
+      p = fv::price_at(F, K, D, sg, fv::sqrt_pos(T), th);
     }
     out[i] = p;
   }
@@ -378,8 +378,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_greeks(KQuotes q, fv_arg sigma, G
         fv::finite_d(qy) && fv::finite_d(sg) && fs > 0.0 && K > 0.0 && T > 0.0 && sg > 0.0 &&
         (th == 1 || th == -1)) {
       const double F = fv::forward_of(MODEL, fs, T, r, qy);
-      const double D = exp(-r * T);
-      const double P = fv::price_at(F, K, D, sg, sqrt(T), th);
+      const double D = fv::fexp(-r * T);
+      const double P = fv::price_at(F, K, D, sg, fv::sqrt_pos(T), th);
       gr = fv::greeks_at(MODEL, fs, K, T, r, qy, sg, th, F, D, P);
     }
     if (g.p[0]) g.p[0][i] = gr.delta;
@@ -444,8 +444,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_price_backward(KQuotes q, fv_arg 
         fv::finite_d(qy) && fv::finite_d(sg) && fs > 0.0 && K > 0.0 && T > 0.0 && sg > 0.0 &&
         (th == 1 || th == -1)) {
       const double F = fv::forward_of(MODEL, fs, T, r, qy);
-      const double D = exp(-r * T);
-      const double P = fv::price_at(F, K, D, sg, sqrt(T), th);
+      const double D = fv::fexp(-r * T);
+      const double P = fv::price_at(F, K, D, sg, fv::sqrt_pos(T), th);
       const fv::PricePartials pp = fv::price_partials(MODEL, fs, K, T, r, qy, sg, th, F, D, P);
       v[0] = g * pp.dfs;
       v[1] = g * pp.dK;
@@ -758,14 +758,17 @@ int device_cus() {
 }
 
 // The configured shape of `kernel`, narrowed for a batch of n quotes too
-// small to keep every CU busy: quotes per thread halve until there are at
-// least two workgroups per CU, and the workgroup drops to one wave if there
-// is still less than one per CU.  Results never depend on the shape.
+// small to keep every SIMD busy: quotes per thread halve until the launch
+// has at least 8 waves per SIMD (32 per CU; fewer, longer waves leave SIMDs
+// idle at the end), and the workgroup drops to one wave if there is still
+// less than one workgroup per CU.  Results never depend on the shape.
 LaunchShape shape_for(int kernel, int64_t n) {
   LaunchShape sh = g_shape[kernel];
   const int64_t cus = device_cus();
-  while (sh.qpt > 1 && (n + (int64_t)sh.block * sh.qpt - 1) / ((int64_t)sh.block * sh.qpt) < 2 * cus)
-    sh.qpt = (sh.qpt + 1) / 2;
+  auto waves = [n](const LaunchShape& t) {
+    return (n + (int64_t)t.block * t.qpt - 1) / ((int64_t)t.block * t.qpt) * (t.block / 64);
+  };
+  while (sh.qpt > 1 && waves(sh) < 32 * cus) sh.qpt = (sh.qpt + 1) / 2;
   if ((n + sh.block - 1) / sh.block < cus) sh.block = 64;
   return sh;
 }

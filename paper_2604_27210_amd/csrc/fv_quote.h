@@ -40,6 +40,15 @@ struct Reduced {
 
 __host__ __device__ inline bool finite_d(double v) { return v - v == 0.0; }
 
+// sqrt(T) for finite T > 0 as T / sqrt(T) from the refined reciprocal
+// square root, with T scaled by 2^200 first when it is so small that
+// v_rsq_f64 could see a denormal
+__host__ __device__ inline double sqrt_pos(double T) {
+  const bool tiny = T < 1e-290;
+  const double Ts = tiny ? T * 0x1p+200 : T;
+  return Ts * rsqrt(Ts) * (tiny ? 0x1p-100 : 1.0);
+}
+
 __host__ __device__ inline double forward_of(int model, double fs, double T, double r,
                                              double q) {
   if (model == kBlack76) return fs;
@@ -62,14 +71,7 @@ __host__ __device__ inline Reduced reduce_quote(int model, double price, double 
   const double M = theta > 0 ? F : K;
   o.F = F;
   o.D = D;
-  // sqrt(T) = T / sqrt(T) from the refined reciprocal square root, with T
-  // scaled by 2^200 first when it is so small that v_rsq_f64 could see a
-  // denormal
-  {
-    const bool tiny = T < 1e-290;
-    const double Ts = tiny ? T * 0x1p+200 : T;
-    o.sqrtT = Ts * rsqrt(Ts) * (tiny ? 0x1p-100 : 1.0);
-  }
+  o.sqrtT = sqrt_pos(T);
   if (Pu < I) { o.status = kQBelowIntrinsic; return o; }
   if (Pu == I) { o.status = kQAtIntrinsic; return o; }
   if (Pu >= M) { o.status = kQAboveMax; return o; }
@@ -103,32 +105,54 @@ struct Greeks {
   double delta, gamma, vega, theta, rho;
 };
 
-__host__ __device__ inline Greeks greeks_at(int model, double fs, double K, double T, double r,
-                                            double q, double sigma, int theta, double F,
-                                            double D, double price) {
+// Terms every closed form below shares, computed once: s = sigma sqrt(T),
+// d1 = ln(F/K)/s + s/2, d2 = d1 - s, Phi(theta d1), Phi(theta d2), phi(d1)
+// and the discounted forward D F (= S e^{-qT} for Black-Scholes(-Merton)).
+struct BsTerms {
+  double sqT, s, d1, d2, N1, N2, n1, DF;
+};
+
+__host__ __device__ inline BsTerms bs_terms(double F, double K, double D, double sigma, double T,
+                                            int theta) {
+  BsTerms c;
+  c.sqT = sqrt_pos(T);
+  c.s = sigma * c.sqT;
+  c.d1 = flog(F / K) / c.s + 0.5 * c.s;
+  c.d2 = c.d1 - c.s;
+  c.N1 = norm_cdf(theta * c.d1);
+  c.N2 = norm_cdf(theta * c.d2);
+  c.n1 = norm_pdf(c.d1);
+  c.DF = D * F;
+  return c;
+}
+
+__host__ __device__ inline Greeks greeks_from(const BsTerms& c, int model, double fs, double K,
+                                              double T, double r, double q, double sigma,
+                                              int theta, double F, double D, double price) {
   Greeks g;
-  const double sqT = sqrt(T);
-  const double s = sigma * sqT;
-  const double d1 = log(F / K) / s + 0.5 * s;
-  const double d2 = d1 - s;
-  const double N1 = norm_cdf(theta * d1), N2 = norm_cdf(theta * d2);
-  const double n1 = norm_pdf(d1);
-  const double DF = D * F;  // = S e^{-qT} for Black-Scholes(-Merton)
-  g.vega = DF * n1 * sqT;
+  g.vega = c.DF * c.n1 * c.sqT;
+  const double decay = 0.5 * sigma * c.DF * c.n1 / c.sqT;  // -dP/dT from the time value
   if (model == kBlack76) {
-    g.delta = theta * D * N1;
-    g.gamma = D * n1 / (F * s);
-    g.theta = r * price - DF * n1 * sigma / (2.0 * sqT);
+    g.delta = theta * D * c.N1;
+    g.gamma = D * c.n1 / (F * c.s);
+    g.theta = r * price - decay;
     g.rho = -T * price;
   } else {
     const double qy = (model == kBlackScholesMerton) ? q : 0.0;
-    const double Dq = DF / fs;  // e^{-qT}
-    g.delta = theta * Dq * N1;
-    g.gamma = Dq * n1 / (fs * s);
-    g.theta = -DF * n1 * sigma / (2.0 * sqT) - theta * r * K * D * N2 + theta * qy * DF * N1;
-    g.rho = theta * K * T * D * N2;
+    const double Dq = c.DF / fs;  // e^{-qT}
+    g.delta = theta * Dq * c.N1;
+    g.gamma = Dq * c.n1 / (fs * c.s);
+    g.theta = -decay - theta * r * K * D * c.N2 + theta * qy * c.DF * c.N1;
+    g.rho = theta * K * T * D * c.N2;
   }
   return g;
+}
+
+__host__ __device__ inline Greeks greeks_at(int model, double fs, double K, double T, double r,
+                                            double q, double sigma, int theta, double F,
+                                            double D, double price) {
+  return greeks_from(bs_terms(F, K, D, sigma, T, theta), model, fs, K, T, r, q, sigma, theta, F,
+                     D, price);
 }
 
 // Partial derivatives of the price at fixed sigma:
@@ -144,14 +168,13 @@ __host__ __device__ inline PricePartials price_partials(int model, double fs, do
                                                         double sigma, int theta, double F,
                                                         double D, double price) {
   PricePartials o;
-  const Greeks g = greeks_at(model, fs, K, T, r, q, sigma, theta, F, D, price);
-  const double s = sigma * sqrt(T);
-  const double d2 = log(F / K) / s - 0.5 * s;
+  const BsTerms c = bs_terms(F, K, D, sigma, T, theta);
+  const Greeks g = greeks_from(c, model, fs, K, T, r, q, sigma, theta, F, D, price);
   o.dfs = g.delta;
-  o.dK = -theta * D * norm_cdf(theta * d2);
+  o.dK = -theta * D * c.N2;
   o.dT = -g.theta;
   o.dr = g.rho;
-  o.dq = (model == kBlackScholesMerton) ? -theta * T * D * F * norm_cdf(theta * (d2 + s)) : 0.0;
+  o.dq = (model == kBlackScholesMerton) ? -theta * T * c.DF * c.N1 : 0.0;
   o.dsigma = g.vega;
   return o;
 }
@@ -169,7 +192,7 @@ __host__ __device__ inline IvGrad iv_gradient(int model, double fs, double K, do
                                               double price) {
   IvGrad o;
   const double F = forward_of(model, fs, T, r, q);
-  const double D = exp(-r * T);
+  const double D = fexp(-r * T);
   const PricePartials pp = price_partials(model, fs, K, T, r, q, sigma, theta, F, D, price);
   const double iv = 1.0 / pp.dsigma;
   o.dP = iv;
@@ -186,11 +209,11 @@ __host__ __device__ inline IvGrad iv_gradient(int model, double fs, double K, do
 // option obtained from the out-of-the-money call by parity.
 __host__ __device__ inline double price_at(double F, double K, double D, double sigma,
                                            double sqrtT, int theta) {
-  const double lx = log(F / K);
+  const double lx = flog(F / K);
   // out-of-the-money side: x_otm <= 0
   const bool itm = theta * lx > 0.0;
   const double x = -fabs(lx);
-  const double bmax = exp(0.5 * x);
+  const double bmax = fexp(0.5 * x);
   const NBlack nb = normalised_black(x, sigma * sqrtT, bmax);
   const double sq = sqrt(F * K);
   double p = D * sq * nb.b;
