@@ -35,6 +35,28 @@ FLAGS = [
 ]
 
 
+DEMO_SRC = os.path.join(CSRC, "fv_capi_demo.c")
+DEMO = os.path.join(OUT_DIR, "fv_capi_demo")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+
+
+def build_capi_demo(verbose: bool = False) -> str:
+    """The plain-C caller of the library (gcc, linked against the built
+    libfastvol.so and the HIP runtime; no Python involved when it runs)."""
+    tmp = DEMO + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(HERE, "..", "include"), "-I", os.path.join(ROCM, "include"),
+           DEMO_SRC, "-o", tmp, "-L", OUT_DIR, "-lfastvol", "-L", os.path.join(ROCM, "lib"),
+           "-lamdhip64", "-lm", "-Wl,-rpath,$ORIGIN", "-Wl,-rpath," + os.path.join(ROCM, "lib")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("gcc failed:\n" + res.stdout + res.stderr)
+    os.replace(tmp, DEMO)
+    return DEMO
+
+
 def build(verbose: bool = False, extra=None, out: str = None) -> str:
     lib = out or LIB
     os.makedirs(os.path.dirname(lib), exist_ok=True)
@@ -56,3 +78,4 @@ def build(verbose: bool = False, extra=None, out: str = None) -> str:
 
 if __name__ == "__main__":
     print(build(verbose=True, extra=sys.argv[1:]))
+    print(build_capi_demo(verbose=True))
