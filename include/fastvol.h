@@ -23,7 +23,8 @@
  *    call only enqueues work and returns; nothing synchronises the host.
  *  - Return value: FV_OK, or a negative fv_status when the call itself is
  *    invalid (nothing is launched; fv_last_error() says why).  n == 0 is a
- *    no-op returning FV_OK.  Per-quote problems never fail a call: they are
+ *    no-op returning FV_OK; n above (2^31 - 1) * 64 (more workgroups than a
+ *    launch can have) is FV_E_INVALID_ARG.  Per-quote problems never fail a call: they are
  *    reported in the per-quote status array (fv_quote_status).
  *  - Black-76 prices are DISCOUNTED (section 2.4): price = e^{-rT} Black(F).
  *    T is in years; r, q continuously compounded.
@@ -246,7 +247,10 @@ int fv_lbr_trace(int model, const fv_quotes *q, uint32_t *path_out, void *stream
 
 /* Launch-shape control.  fv_set_launch(kernel, block, quotes_per_thread)
  * overrides the launch shape of one kernel family (FV_KERNEL_*); block must
- * be a multiple of 64 in [64, 512] and quotes_per_thread in [1, 16].
+ * be a multiple of 64 in [64, 512] and quotes_per_thread in [1, 16], and for
+ * the Halley families the workgroup's queue of unconverged quotes (24 bytes
+ * per quote, 16 for binary32) must fit in 64 KiB of LDS
+ * (FV_E_INVALID_ARG otherwise; the shape in force is kept).
  * fv_get_launch reads the current shape.  The shape applies as set to
  * batches large enough to fill the device; a batch that would give fewer
  * than 8 waves per SIMD (32 per compute unit) runs with fewer quotes per

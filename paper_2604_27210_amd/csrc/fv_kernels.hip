@@ -714,11 +714,27 @@ bool valid_shape(int block, int qpt) {
   return block >= 64 && block <= kMaxBlock && block % 64 == 0 && qpt >= 1 && qpt <= 16;
 }
 
+// Dynamic LDS a kernel family needs per workgroup at a shape: the Halley
+// paths' queue of failed lanes (one entry per quote of the workgroup); no
+// other family uses dynamic LDS.  Shapes above kMaxQueueBytes are refused.
+constexpr size_t kMaxQueueBytes = 65536;
+
+size_t queue_bytes(int kernel, int block, int qpt) {
+  if (kernel == FV_KERNEL_IV_HALLEY) return sizeof(Pending) * (size_t)block * qpt;
+  if (kernel == FV_KERNEL_IV_HALLEY_F32) return sizeof(Pending32) * (size_t)block * qpt;
+  return 0;
+}
+
+// Largest batch any launch covers: every launch has at least 64 quotes per
+// workgroup and at most 2^31 - 1 workgroups.
+constexpr int64_t kMaxQuotes = (int64_t)0x7fffffff * 64;
+
 int check_quotes(int model, const fv_quotes* q) {
   if (model < FV_MODEL_BLACK76 || model > FV_MODEL_BSM)
     return fail(FV_E_INVALID_ARG, "model out of range");
   if (!q) return fail(FV_E_INVALID_ARG, "quotes pointer is NULL");
   if (q->n < 0) return fail(FV_E_INVALID_ARG, "n < 0");
+  if (q->n > kMaxQuotes) return fail(FV_E_INVALID_ARG, "n above 2^31 - 1 workgroups of 64");
   if (!q->flag && q->flag_value != 1 && q->flag_value != -1)
     return fail(FV_E_INVALID_ARG, "broadcast flag_value must be +1 or -1");
   return FV_OK;
@@ -785,6 +801,8 @@ const char* fv_last_error(void) { return fvh::g_last_error.c_str(); }
 int fv_set_launch(int kernel, int block, int qpt) {
   if (kernel < 0 || kernel >= FV_KERNEL_COUNT) return fail(FV_E_INVALID_ARG, "kernel id");
   if (!valid_shape(block, qpt)) return fail(FV_E_INVALID_ARG, "launch shape");
+  if (queue_bytes(kernel, block, qpt) > kMaxQueueBytes)
+    return fail(FV_E_INVALID_ARG, "launch shape: Halley queue above 64 KiB of LDS");
   g_shape[kernel].block = block;
   g_shape[kernel].qpt = qpt;
   return FV_OK;
@@ -868,6 +886,7 @@ int fv_implied_vol_f32(int model, const fv_quotes_f32* q, float* sigma_out,
     return fail(FV_E_INVALID_ARG, "model out of range");
   if (!q) return fail(FV_E_INVALID_ARG, "quotes pointer is NULL");
   if (q->n < 0) return fail(FV_E_INVALID_ARG, "n < 0");
+  if (q->n > kMaxQuotes) return fail(FV_E_INVALID_ARG, "n above 2^31 - 1 workgroups of 64");
   if (!q->flag && q->flag_value != 1 && q->flag_value != -1)
     return fail(FV_E_INVALID_ARG, "broadcast flag_value must be +1 or -1");
   if (q->n == 0) return FV_OK;
@@ -1154,6 +1173,7 @@ int fv_autotune(int kernel, int model, int64_t n_hint, void* stream) {
   for (int b : blocks) {
     for (int qq : qpts) {
       if (rc != FV_OK) break;
+      if (queue_bytes(kernel, b, qq) > kMaxQueueBytes) continue;
       g_shape[kernel] = {b, qq};
       rc = run();  // warm-up
       float tot = 0.0f, mn = 1e30f;

@@ -52,6 +52,17 @@ def test_version_and_error_paths(lib):
     b, q = ctypes.c_int(), ctypes.c_int()
     assert lib.fv_get_launch(1, ctypes.byref(b), ctypes.byref(q)) == N.FV_OK
     assert b.value % 64 == 0 and q.value >= 1
+    # Halley shapes whose LDS queue would exceed 64 KiB are refused; the
+    # shape in force is left as it was
+    for kern in (2, 6):
+        assert lib.fv_get_launch(kern, ctypes.byref(b), ctypes.byref(q)) == N.FV_OK
+        saved = (b.value, q.value)
+        assert lib.fv_set_launch(kern, 512, 16) == N.FV_E_INVALID_ARG
+        assert b"LDS" in lib.fv_last_error()
+        assert lib.fv_get_launch(kern, ctypes.byref(b), ctypes.byref(q)) == N.FV_OK
+        assert (b.value, q.value) == saved
+    assert lib.fv_set_launch(0, 512, 16) == N.FV_OK  # no queue: any valid shape
+    assert lib.fv_set_launch(0, 256, 1) == N.FV_OK
     # invalid model / solver / NULL outputs are refused before any launch
     qs = N.FvQuotes(4, N.FvArg(None, 1.0), N.FvArg(None, 100.0), N.FvArg(None, 100.0),
                     N.FvArg(None, 1.0), N.FvArg(None, 0.0), N.FvArg(None, 0.0), None, 1)
@@ -68,6 +79,11 @@ def test_version_and_error_paths(lib):
     bad_flag = N.FvQuotes(4, N.FvArg(None, 1.0), N.FvArg(None, 100.0), N.FvArg(None, 100.0),
                           N.FvArg(None, 1.0), N.FvArg(None, 0.0), N.FvArg(None, 0.0), None, 0)
     assert lib.fv_price(2, ctypes.byref(bad_flag), N.FvArg(None, 0.2), dummy, None) == N.FV_E_INVALID_ARG
+    huge = N.FvQuotes((1 << 31) * 64, N.FvArg(None, 1.0), N.FvArg(None, 100.0),
+                      N.FvArg(None, 100.0), N.FvArg(None, 1.0), N.FvArg(None, 0.0),
+                      N.FvArg(None, 0.0), None, 1)
+    assert lib.fv_implied_vol(2, 0, ctypes.byref(huge), dummy, None, None, None) == N.FV_E_INVALID_ARG
+    assert b"2^31" in lib.fv_last_error()
     assert lib.fv_implied_vol_chains(0, None, dummy, None, None) == N.FV_E_INVALID_ARG
     assert lib.fv_normalised_black(-1, None, None, None, None, None) == N.FV_E_INVALID_ARG
     # n == 0 is a no-op
