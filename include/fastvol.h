@@ -32,7 +32,9 @@
  *    Black-76), gamma = d2P/dS2, vega = dP/dsigma, theta = -dP/dT per year,
  *    rho = dP/dr (Black-76: at fixed F).
  *  - Not thread-safe across concurrent calls that share output buffers;
- *    otherwise calls from several host threads are independent.
+ *    otherwise calls from several host threads are independent, except that
+ *    fv_set_launch and fv_autotune change process-wide launch shapes and
+ *    must not run while another thread launches.
  */
 #ifndef FASTVOL_H
 #define FASTVOL_H
