@@ -239,8 +239,22 @@ def extras(fv, torch, main_inputs):
         fv.implied_vol_backward("bsm", Pd, x[0], x[1], x[2], x[3], sig, w, flag=fld, q=x[4])
     ms_fb = _time(torch, fwd_bwd)
     ms_fw = _time(torch, lambda: fv.implied_vol("bsm", Pd, x[0], x[1], x[2], x[3], flag=fld, q=x[4]))
+    # the configuration as stated: forward IV with the five Greeks fused in,
+    # backward through torch.autograd to all six inputs, L = sum(w sigma)
+    leaves = [t.clone().requires_grad_(True) for t in [Pd] + x]
+
+    def fwd_bwd_autograd():
+        for t in leaves:
+            t.grad = None
+        sig, st, gk = fv.implied_vol_autograd("bsm", *leaves[:5], flag=fld, q=leaves[5],
+                                              greeks=True)
+        (w * sig).sum().backward()
+    ms_ag = _time(torch, fwd_bwd_autograd)
     out["bsm_1m_fwd_bwd"] = {"ms": ms_fb, "quotes_per_s": wd.n / ms_fb * 1e3,
-                             "forward_only_ms": ms_fw}
+                             "forward_only_ms": ms_fw,
+                             "calls": "fv_implied_vol + fv_implied_vol_backward",
+                             "autograd_with_greeks_ms": ms_ag,
+                             "autograd_with_greeks_quotes_per_s": wd.n / ms_ag * 1e3}
     # calibration loop: 500 chains, 200 Adam steps, one hipGraph replay per step
     cal = W.svi_calibration(500, seed=5)
     chc = cal.chains

@@ -121,28 +121,38 @@ def price(model, fs, K, T, r, sigma, flag="c", q=None, out=None, stream=None) ->
     return out
 
 
-def implied_vol(model, price, fs, K, T, r, flag="c", q=None, solver="lbr", greeks=False,
-                with_status=True, stream=None):
-    """Implied volatility.  Returns sigma, or (sigma, status) with
-    ``with_status``; with ``greeks=True`` a dict of the five Greeks at the
-    solved sigma is appended."""
+GREEK_NAMES = ("delta", "gamma", "vega", "theta", "rho")
+
+
+def _implied_vol(model, price, fs, K, T, r, flag, q, solver, greeks, with_status, stream):
+    """(sigma, status or None, Greeks as one [5, n] tensor or None)."""
     b = _Batch(price=price, fs=fs, K=K, T=T, r=r, q=q, flag=flag)
     qs = b.quotes(price, fs, K, T, r, q, flag)
     sig = b.empty()
     st = b.empty(torch.uint8) if with_status else None
-    gk = None
+    G = None
     garr = None
     if greeks:
-        gk = {k: b.empty() for k in ("delta", "gamma", "vega", "theta", "rho")}
-        garr = (ctypes.c_void_p * 5)(*[g.data_ptr() for g in gk.values()])
+        G = torch.empty((5, b.n), dtype=torch.float64, device=b.device)
+        garr = (ctypes.c_void_p * 5)(*[G[i].data_ptr() for i in range(5)])
     N.check(N.load().fv_implied_vol(_model(model), _solver(solver), ctypes.byref(qs), _ptr(sig),
                                     _ptr(st), garr, ctypes.c_void_p(_stream_ptr(stream))),
             "fv_implied_vol")
+    return sig, st, G
+
+
+def implied_vol(model, price, fs, K, T, r, flag="c", q=None, solver="lbr", greeks=False,
+                with_status=True, stream=None):
+    """Implied volatility.  Returns sigma, or (sigma, status) with
+    ``with_status``; with ``greeks=True`` a dict of the five Greeks at the
+    solved sigma is appended (rows of one [5, n] tensor)."""
+    sig, st, G = _implied_vol(model, price, fs, K, T, r, flag, q, solver, greeks, with_status,
+                              stream)
     res = [sig]
     if with_status:
         res.append(st)
     if greeks:
-        res.append(gk)
+        res.append({k: G[i] for i, k in enumerate(GREEK_NAMES)})
     return res[0] if len(res) == 1 else tuple(res)
 
 

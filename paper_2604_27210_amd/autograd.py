@@ -23,19 +23,22 @@ def _req(t):
 
 class IVFunction(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, price, fs, K, T, r, q, flag, model, solver):
-        sig, st = api.implied_vol(model, price.detach(), _d(fs), _d(K), _d(T), _d(r),
-                                  flag=flag, q=_d(q), solver=solver)
+    def forward(ctx, price, fs, K, T, r, q, flag, model, solver, greeks):
+        sig, st, G = api._implied_vol(model, price.detach(), _d(fs), _d(K), _d(T), _d(r), flag,
+                                      _d(q), solver, greeks, True, None)
         ctx.model = model
         ctx.flag = flag
         ctx.scalar = [not isinstance(v, torch.Tensor) or v.dim() == 0 for v in (price, fs, K, T, r, q)]
         ctx.save_for_backward(*[v if isinstance(v, torch.Tensor) else torch.tensor(float(v or 0.0))
                                 for v in (price, fs, K, T, r, q)], sig)
-        ctx.mark_non_differentiable(st)
-        return sig, st
+        # the five Greeks leave as one [5, n] tensor: every extra output of a
+        # Function costs the autograd engine bookkeeping
+        extra = (G,) if greeks else ()
+        ctx.mark_non_differentiable(st, *extra)
+        return (sig, st) + extra
 
     @staticmethod
-    def backward(ctx, g_sig, g_st):
+    def backward(ctx, g_sig, g_st, *g_greeks):
         price, fs, K, T, r, q, sig = ctx.saved_tensors
         args = [v.item() if s else v.detach() for v, s in zip((price, fs, K, T, r, q), ctx.scalar)]
         g = api.implied_vol_backward(ctx.model, args[0], args[1], args[2], args[3], args[4],
@@ -44,17 +47,24 @@ class IVFunction(torch.autograd.Function):
         for name, s, need in zip(("price", "fs", "K", "T", "r", "q"), ctx.scalar,
                                  ctx.needs_input_grad[:6]):
             outs.append(g[name] if (need and not s) else None)
-        return (*outs, None, None, None)
+        return (*outs, None, None, None, None)
 
 
 def _d(v):
     return v.detach() if isinstance(v, torch.Tensor) else v
 
 
-def implied_vol_autograd(model, price, fs, K, T, r, flag="c", q=None, solver="lbr"):
+def implied_vol_autograd(model, price, fs, K, T, r, flag="c", q=None, solver="lbr",
+                         greeks=False):
     """Implied volatility with gradients to every tensor input.  Returns
-    (sigma, status); status is not differentiable."""
-    return IVFunction.apply(price, fs, K, T, r, q, flag, model, solver)
+    (sigma, status), or (sigma, status, greeks) with ``greeks=True``: the
+    five Greeks at the solved sigma from the same fused launch, as a dict
+    (delta, gamma, vega, theta, rho).  Status and Greeks are not
+    differentiable."""
+    out = IVFunction.apply(price, fs, K, T, r, q, flag, model, solver, bool(greeks))
+    if not greeks:
+        return out
+    return out[0], out[1], {k: out[2][i] for i, k in enumerate(api.GREEK_NAMES)}
 
 
 class PriceFunction(torch.autograd.Function):

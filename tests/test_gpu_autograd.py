@@ -140,3 +140,27 @@ def test_price_adjoint_matches_oracle_greeks(fv):
         a = t.grad.cpu().numpy()
         rel = np.abs(a - ref) / np.maximum(np.abs(ref), 1e-300)
         assert np.quantile(rel, 0.999) < 1e-9
+
+
+def test_autograd_with_fused_greeks(fv):
+    """greeks=True returns the fused launch's Greeks (bitwise those of the
+    plain call) and leaves sigma and every gradient unchanged."""
+    wl = W.bsm_diff(30_000, seed=47)
+    P = assemble_prices(wl)
+    fl = dev(wl.flag, torch.int8)
+    grads = []
+    for greeks in (False, True):
+        ins = [dev(a, grad=True) for a in (P, wl.fs, wl.K, wl.T, wl.r, wl.q)]
+        out = fv.implied_vol_autograd("bsm", *ins[:5], flag=fl, q=ins[5], greeks=greeks)
+        (dev(wl.extra["w"]) * out[0]).sum().backward()
+        grads.append([t.grad.clone() for t in ins] + [out[0].detach()])
+        if greeks:
+            gk = out[2]
+            assert set(gk) == {"delta", "gamma", "vega", "theta", "rho"}
+            assert not any(t.requires_grad for t in gk.values())
+            _, _, ref = fv.implied_vol("bsm", *[t.detach() for t in ins[:5]], flag=fl,
+                                       q=ins[5].detach(), greeks=True)
+            for k in gk:
+                assert torch.equal(torch.nan_to_num(gk[k], nan=-1.0), torch.nan_to_num(ref[k], nan=-1.0)), k
+    for a, b in zip(*grads):
+        assert torch.equal(torch.nan_to_num(a, nan=-1.0), torch.nan_to_num(b, nan=-1.0))
