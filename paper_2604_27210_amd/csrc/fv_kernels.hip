@@ -706,7 +706,7 @@ LaunchShape g_shape[FV_KERNEL_COUNT] = {
     {128, 4},  // IV Halley
     {256, 1},  // Greeks
     {256, 1},  // backward
-    {256, 8},  // chains
+    {128, 8},  // chains
     {128, 4},  // IV Halley, binary32
 };
 
