@@ -71,7 +71,10 @@ enum fv_quote_status {
     FV_Q_AT_INTRINSIC = 1,     /* undiscounted price == intrinsic: sigma = 0    */
     FV_Q_BELOW_INTRINSIC = 2,  /* price below intrinsic: sigma = NaN            */
     FV_Q_ABOVE_MAX = 3,        /* price >= the no-arbitrage maximum: NaN        */
-    FV_Q_INVALID_INPUT = 4,    /* non-finite input, S/F, K or T <= 0, bad flag  */
+    FV_Q_INVALID_INPUT = 4,    /* non-finite input, S/F, K or T <= 0, bad flag;
+                                  for the implied-volatility entry points also
+                                  S/F, K or the forward below the smallest
+                                  normal number (or the forward overflowing) */
     FV_Q_NOT_CONVERGED = 5     /* solver did not meet its tolerance (sigma kept) */
 };
 

@@ -33,8 +33,11 @@ constexpr float kLog2E = 1.44269504088896341f;
 constexpr float kLn2Hi = 0.693145751953125f;      // 15 significant bits: n kLn2Hi exact
 constexpr float kLn2Lo = 1.42860682030941723e-6f;  // ln 2 - kLn2Hi
 constexpr float kBetaMin = 7.8886090522101181e-31f;  // 2^-100
+constexpr float kFltMin = 1.17549435082228751e-38f;  // smallest normal binary32
 
-__host__ __device__ inline bool finite(float v) { return v - v == 0.0f; }
+// by classification, not v - v == 0 (contraction would turn that into the
+// rounding error of a product)
+__host__ __device__ inline bool finite(float v) { return __builtin_isfinite(v); }
 
 __host__ __device__ inline float rcp(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -144,11 +147,12 @@ __host__ __device__ inline Reduced reduce_quote(int model, float price, float fs
   Reduced o;
   o.x = o.beta = o.bmax = o.lnb = o.sqrtT = 0.0f;
   const bool ok_in = finite(price) && finite(fs) && finite(K) && finite(T) && finite(r) &&
-                     finite(q) && fs > 0.0f && K > 0.0f && T > 0.0f &&
+                     finite(q) && fs >= kFltMin && K >= kFltMin && T > 0.0f &&
                      (theta == 1 || theta == -1);
   if (!ok_in) { o.status = 4; return o; }
   const float carry = model == 0 ? 0.0f : (model == 2 ? r - q : r);
   const float F = model == 0 ? fs : fs * fexp(carry * T);
+  if (!(F >= kFltMin && finite(F))) { o.status = 4; return o; }
   const float Pu = price * fexp(r * T);
   const float I = theta > 0 ? fmaxf(F - K, 0.0f) : fmaxf(K - F, 0.0f);
   const float M = theta > 0 ? F : K;
@@ -159,7 +163,7 @@ __host__ __device__ inline Reduced reduce_quote(int model, float price, float fs
   const int th = (I > 0.0f) ? -theta : theta;
   const float lx = flog(F * rcp(K));
   o.x = th > 0 ? lx : -lx;
-  const float isq = rsqrt(F * K);
+  const float isq = rsqrt(F) * rsqrt(K);  // F K leaves binary32 beyond about 1e+-19
   o.beta = (Pu - I) * isq;
   o.bmax = fminf(F, K) * isq;
   o.status = (o.beta < o.bmax) ? 0 : 3;

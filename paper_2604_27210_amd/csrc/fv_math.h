@@ -30,6 +30,7 @@ constexpr double kLnSqrt2Pi = 0.91893853320467274178;
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kSqrt3 = 1.73205080756887729353;
 constexpr double kEps = 2.220446049250313e-16;
+constexpr double kDblMin = 2.2250738585072014e-308;  // smallest normal binary64
 
 // ----------------------------------------------------------- reciprocal
 // 1/x for finite, normal, non-zero x: the hardware estimate v_rcp_f64

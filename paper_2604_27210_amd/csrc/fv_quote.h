@@ -38,7 +38,10 @@ struct Reduced {
   uint8_t status;
 };
 
-__host__ __device__ inline bool finite_d(double v) { return v - v == 0.0; }
+// Finite test by classification (v_cmp_class), never by arithmetic: with
+// contraction on, v - v == 0 for a product v = a b compiles to
+// fma(a, b, -v) == 0, the product's rounding error, which is rarely 0.
+__host__ __device__ inline bool finite_d(double v) { return __builtin_isfinite(v); }
 
 // sqrt(T) for finite T > 0 as T / sqrt(T) from the refined reciprocal
 // square root, with T scaled by 2^200 first when it is so small that
@@ -60,11 +63,14 @@ __host__ __device__ inline Reduced reduce_quote(int model, double price, double 
                                                 double T, double r, double q, int theta) {
   Reduced o;
   o.F = 0.0; o.D = 0.0; o.sqrtT = 0.0; o.x = 0.0; o.beta = 0.0; o.bmax = 0.0; o.lnb = 0.0;
+  // S/F and K must be normal numbers (the refined hardware reciprocals
+  // below need normal operands); so must the forward
   const bool ok_in = finite_d(price) && finite_d(fs) && finite_d(K) && finite_d(T) &&
-                     finite_d(r) && finite_d(q) && fs > 0.0 && K > 0.0 && T > 0.0 &&
+                     finite_d(r) && finite_d(q) && fs >= kDblMin && K >= kDblMin && T > 0.0 &&
                      (theta == 1 || theta == -1);
   if (!ok_in) { o.status = kQInvalid; return o; }
   const double F = forward_of(model, fs, T, r, q);
+  if (!(F >= kDblMin && finite_d(F))) { o.status = kQInvalid; return o; }
   const double D = fexp(-r * T);
   const double Pu = price * fexp(r * T);
   const double I = theta > 0 ? fmax(F - K, 0.0) : fmax(K - F, 0.0);
@@ -78,7 +84,9 @@ __host__ __device__ inline Reduced reduce_quote(int model, double price, double 
   const int th = (I > 0.0) ? -theta : theta;  // in the money: parity to OTM
   const double lx = flog(F * rcp(K));
   o.x = th > 0 ? lx : -lx;
-  const double isq = rsqrt(F * K);
+  // 1/sqrt(F K) as two factors: F K itself leaves the binary64 range once F
+  // and K are beyond about 1e+-154, while the normalised quantities do not
+  const double isq = rsqrt(F) * rsqrt(K);
   o.beta = (Pu - I) * isq;
   o.bmax = fmin(F, K) * isq;
   // the normalised price can round onto its bound even when Pu < M
@@ -86,7 +94,7 @@ __host__ __device__ inline Reduced reduce_quote(int model, double price, double 
   if (o.beta < 0x1p-1000 && I == 0.0) {
     // out of the money with a price too small for beta to keep full precision
     // in binary64: ln beta = ln P + r T - ln(F K)/2 from the price itself
-    o.lnb = flog(price) + r * T - 0.5 * flog(F * K);
+    o.lnb = flog(price) + r * T - 0.5 * (flog(F) + flog(K));
   } else {
     o.lnb = flog(o.beta);
   }
@@ -215,7 +223,7 @@ __host__ __device__ inline double price_at(double F, double K, double D, double 
   const double x = -fabs(lx);
   const double bmax = fexp(0.5 * x);
   const NBlack nb = normalised_black(x, sigma * sqrtT, bmax);
-  const double sq = sqrt(F * K);
+  const double sq = sqrt(F) * sqrt(K);  // F K may leave the binary64 range
   double p = D * sq * nb.b;
   if (itm) p += D * (theta > 0 ? (F - K) : (K - F));
   return p;

@@ -331,3 +331,36 @@ def test_autotune_picks_a_valid_shape_and_results_do_not_change(fv):
     finally:
         for k, (b, q) in saved.items():
             fv.set_launch(k, b, q)
+
+
+def test_scale_invariance(fv):
+    """The implied volatility is homogeneous of degree 0 in (price, S, K):
+    scaling all three by 2^k (even k, exact in binary64) must give bitwise
+    the unscaled result, also where F K itself leaves the binary64 range
+    (|k| >= 600); inputs below the normal range are invalid."""
+    rng = np.random.default_rng(5)
+    n = 4096
+    S = np.full(n, 100.0)
+    K = 100.0 * np.exp(rng.uniform(-0.5, 0.5, n))
+    T = rng.uniform(0.1, 2.0, n)
+    r = np.full(n, 0.03)
+    q = np.full(n, 0.01)
+    sig = rng.uniform(0.1, 0.6, n)
+    fl = np.where(np.arange(n) % 2 == 0, 1, -1).astype(np.int8)
+    P = oracle.price("bsm", S, K, T, r, q, sig, fl)
+    for solver in ("lbr", "halley"):
+        ref = None
+        for k in (0, 300, 600, 900, -300, -600):
+            f = 2.0 ** k
+            s, st = fv.implied_vol("bsm", dev(P * f), dev(S * f), dev(K * f), dev(T), dev(r),
+                                   flag=dev(fl, torch.int8), q=dev(q), solver=solver)
+            s, st = host(s), host(st)
+            if ref is None:
+                ref = (s, st)
+                assert (st == 0).mean() > 0.97
+            assert np.array_equal(st, ref[1]), (solver, k)
+            assert np.array_equal(np.nan_to_num(s, nan=-1.0), np.nan_to_num(ref[0], nan=-1.0)), (solver, k)
+    # S or K below the smallest normal binary64: invalid, not garbage
+    s, st = fv.implied_vol("bs", dev(np.array([5.0, 5.0])), dev(np.array([1e-310, 100.0])),
+                           dev(np.array([100.0, 1e-310])), 1.0, 0.0, flag="c")
+    assert list(host(st)) == [4, 4] and np.all(np.isnan(host(s)))
