@@ -35,9 +35,9 @@ if ROOT not in sys.path:
 # The traffic figure is reported only while the kernel sources still hash to
 # ``source_sha256``; the FLOP figure is the algorithmic count of that source.
 LBR_PROFILE = {
-    "source_sha256": "c7f6ff1fd2f5d02e24a27b474b42790f054b6ab4fb13bfbe5701193b1c509b2c",
-    "flop_per_quote": 1158.3,
-    "fetch_bytes_per_quote": 49.040,
+    "source_sha256": "1e24e0d707b5e9acc6b0fb5df5f355a29f7e10dbea1f9e66bc7c4d4b10fc3f3e",
+    "flop_per_quote": 1161.8,
+    "fetch_bytes_per_quote": 49.038,
     "write_bytes_per_quote": 9.008,
 }
 FP64_VECTOR_PEAK_TFLOPS = 78.6
