@@ -20,7 +20,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fv_oracle.c")
 _OUT_DIR = os.path.join(_HERE, "_build")
-_LIB_PATH = os.path.join(_OUT_DIR, "libfv_oracle.so")
+# FV_ORACLE_LIB names another build of the oracle to load instead (the
+# mutation test points the pins at deliberately broken copies this way)
+_LIB_PATH = os.environ.get("FV_ORACLE_LIB") or os.path.join(_OUT_DIR, "libfv_oracle.so")
 
 MODELS = {"black76": 0, "bs": 1, "bsm": 2}
 # status numbering of the oracle (mirrors the documented per-quote codes)
@@ -29,17 +31,19 @@ ST_OK, ST_AT, ST_BELOW, ST_ABOVE, ST_INVALID, ST_NO_EXACT_ROOT, ST_ROOT_CAP = 0,
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no fast-math, no FP contraction)."""
-    if not force and os.path.exists(_LIB_PATH):
-        return _LIB_PATH
-    os.makedirs(_OUT_DIR, exist_ok=True)
-    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+def build(force: bool = True, src: str = _SRC, out: str = None) -> str:
+    """Compile the oracle with gcc (no fast-math, no FP contraction); `src`
+    and `out` default to fv_oracle.c and the library this module loads."""
+    out = out or _LIB_PATH
+    if not force and os.path.exists(out):
+        return out
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared",
-           "-fPIC", _SRC, "-o", tmp, "-lquadmath", "-lm"]
+           "-fPIC", src, "-o", tmp, "-lquadmath", "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    os.replace(tmp, out)
+    return out
 
 
 def _load():

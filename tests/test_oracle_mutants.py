@@ -1,0 +1,89 @@
+"""The oracle's pins catch plausible mistakes (CPU only).
+
+Each mutant is fv_oracle.c with one deliberate slip -- a dropped term, a
+wrong sign, a swapped operand or index, a put branch that lost its flag --
+compiled into a library of its own; the pin suite (tests/test_oracle_pins.py)
+then runs against it in a child process (FV_ORACLE_LIB selects the build)
+and must fail.  The unmutated oracle passes the same suite in the main run.
+The mistakes are planted in the oracle's source text, on the CPU; nothing
+here touches the GPU library."""
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+import oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+PINS = os.path.join(HERE, "test_oracle_pins.py")
+
+# (what goes wrong, the oracle's text, the mistaken text)
+MUTANTS = [
+    ("Black-76 price not discounted",
+     "return D * th * (a->fs * q_Phi(th * d1) - a->K * q_Phi(th * d2));",
+     "return th * (a->fs * q_Phi(th * d1) - a->K * q_Phi(th * d2));"),
+    ("Black-76 d2 = d1 + s",
+     "qr d1 = (logq(a->fs / a->K) + 0.5Q * sigma * sigma * a->T) / sd;\n        qr d2 = d1 - sd;",
+     "qr d1 = (logq(a->fs / a->K) + 0.5Q * sigma * sigma * a->T) / sd;\n        qr d2 = d1 + sd;"),
+    ("BSM price: carry r + q",
+     "(logq(a->fs / a->K) + (a->r - qy + 0.5Q * sigma * sigma) * a->T) / sd;",
+     "(logq(a->fs / a->K) + (a->r + qy + 0.5Q * sigma * sigma) * a->T) / sd;"),
+    ("forward: carry r + q",
+     "qr carry = (a->model == ORC_BSM) ? (a->r - a->q) : a->r;",
+     "qr carry = (a->model == ORC_BSM) ? (a->r + a->q) : a->r;"),
+    ("BSM put: Phi(d2) without the flag",
+     "- a->K * D * q_Phi(th * d2));",
+     "- a->K * D * q_Phi(d2));"),
+    ("BSM vega without sqrt(T)",
+     "out[2] = S * Dq * q_phi(d1) * sqT;",
+     "out[2] = S * Dq * q_phi(d1);"),
+    ("BSM gamma without sigma",
+     "out[1] = Dq * q_phi(d1) / (S * sigma * sqT);",
+     "out[1] = Dq * q_phi(d1) / (S * sqT);"),
+    ("Black-76 theta: sign of r P",
+     "out[3] = a->r * P - D * F * q_phi(d1) * sigma / (2 * sqT);",
+     "out[3] = -a->r * P - D * F * q_phi(d1) * sigma / (2 * sqT);"),
+    ("Black-76 rho: sign",
+     "out[4] = -a->T * P;",
+     "out[4] = a->T * P;"),
+    ("dP/dK with d1",
+     "dP[1] = -th * D * q_Phi(th * d2);",
+     "dP[1] = -th * D * q_Phi(th * d1);"),
+    ("IV gradient: sign of dsigma/dX",
+     "g[1 + j] = (double)(-dP[j] / v);",
+     "g[1 + j] = (double)(dP[j] / v);"),
+    ("normalised Black: e^{x/2} and e^{-x/2} swapped",
+     "b = th * (expq(X / 2) * q_Phi(th * (h + t)) - expq(-X / 2) * q_Phi(th * (h - t)));",
+     "b = th * (expq(-X / 2) * q_Phi(th * (h + t)) - expq(X / 2) * q_Phi(th * (h - t)));"),
+    ("status: upper bound of a put is F",
+     "double M = theta > 0 ? F : K;",
+     "double M = theta > 0 ? F : F;"),
+]
+
+
+def _run_pins(name, old, new, workdir):
+    with open(oracle._SRC) as fh:
+        src = fh.read()
+    assert src.count(old) == 1, "mutation site not unique: " + name
+    tag = "m%02d" % [m[0] for m in MUTANTS].index(name)
+    csrc = os.path.join(workdir, tag + ".c")
+    with open(csrc, "w") as fh:
+        fh.write(src.replace(old, new))
+    lib = oracle.build(src=csrc, out=os.path.join(workdir, "lib" + tag + ".so"))
+    env = dict(os.environ, FV_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
+    res = subprocess.run([sys.executable, "-m", "pytest", PINS, "-x", "-q", "-p", "no:cacheprovider",
+                          "-m", "not gpu"], cwd=ROOT, env=env, capture_output=True, text=True,
+                         timeout=900)
+    return name, res.returncode, res.stdout[-1500:]
+
+
+def test_every_mutant_fails_a_pin(tmp_path):
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        results = list(ex.map(lambda m: _run_pins(m[0], m[1], m[2], str(tmp_path)), MUTANTS))
+    survivors = [(name, out) for name, rc, out in results if rc != 1]
+    # pytest exits 1 when a test failed; anything else (0 = all passed,
+    # 2+ = the run itself broke) means the pins did not catch the slip
+    assert not survivors, survivors
