@@ -1,4 +1,5 @@
-"""The oracle's pins catch plausible mistakes (CPU only).
+"""The oracle's pins catch plausible mistakes (CPU only): the binary128 C
+oracle and the numpy calibration reference.
 
 Each mutant is fv_oracle.c with one deliberate slip -- a dropped term, a
 wrong sign, a swapped operand or index, a put branch that lost its flag --
@@ -64,11 +65,10 @@ MUTANTS = [
 ]
 
 
-def _run_pins(name, old, new, workdir):
+def _run_pins(tag, name, old, new, workdir):
     with open(oracle._SRC) as fh:
         src = fh.read()
     assert src.count(old) == 1, "mutation site not unique: " + name
-    tag = "m%02d" % [m[0] for m in MUTANTS].index(name)
     csrc = os.path.join(workdir, tag + ".c")
     with open(csrc, "w") as fh:
         fh.write(src.replace(old, new))
@@ -80,10 +80,64 @@ def _run_pins(name, old, new, workdir):
     return name, res.returncode, res.stdout[-1500:]
 
 
-def test_every_mutant_fails_a_pin(tmp_path):
+# Slips in the numpy SVI reference (oracle/svi.py), caught by
+# tests/test_oracle_svi.py: each runs from a temporary copy of the oracle
+# package whose svi.py carries the slip, placed first on the import path.
+SVI_MUTANTS = [
+    ("softplus derivative of b~ at -b~",
+     "(rho[mat] * dk + rt) * sg(raw[mat, 1])", "(rho[mat] * dk + rt) * sg(-raw[mat, 1])"),
+    ("tanh derivative dropped from d/drho~",
+     "b[mat] * dk * (1.0 - rho[mat] ** 2)", "b[mat] * dk"),
+    ("d/dm: sign of the root term",
+     "b[mat] * (-rho[mat] - dk / rt)", "b[mat] * (-rho[mat] + dk / rt)"),
+    ("total variance: s instead of s^2 under the root",
+     "np.sqrt(dk * dk + s[mat] ** 2))\n", "np.sqrt(dk * dk + s[mat]))\n"),
+    ("loss halved",
+     "L = np.sum(e * e) / N", "L = np.sum(e * e) / (2 * N)"),
+    ("Adam without the second bias correction",
+     "vh = vo / (1 - b2 ** t)", "vh = vo"),
+]
+SVI_PINS = os.path.join(HERE, "test_oracle_svi.py")
+
+
+def _run_svi_pins(tag, name, old, new, workdir):
+    import shutil
+    d = os.path.join(workdir, tag)
+    pkg = os.path.join(d, "oracle")
+    os.makedirs(pkg)
+    src_dir = os.path.dirname(oracle._SRC)
+    shutil.copy(os.path.join(src_dir, "__init__.py"), pkg)
+    with open(os.path.join(src_dir, "svi.py")) as fh:
+        src = fh.read()
+    assert src.count(old) == 1, "mutation site not unique: " + name
+    with open(os.path.join(pkg, "svi.py"), "w") as fh:
+        fh.write(src.replace(old, new))
+    shutil.copy(SVI_PINS, d)
+    env = dict(os.environ, PYTHONPATH=ROOT, FV_ORACLE_LIB=oracle._LIB_PATH)
+    res = subprocess.run([sys.executable, "-m", "pytest", "test_oracle_svi.py", "-x", "-q",
+                          "-p", "no:cacheprovider"], cwd=d, env=env, capture_output=True,
+                         text=True, timeout=900)
+    return name, res.returncode, res.stdout[-1500:]
+
+
+def _check(run, mutants, workdir):
+    # job 0 is a control: the same harness on an unchanged copy must pass
+    jobs = [("c00", "control: unchanged", mutants[0][1], mutants[0][1])]
+    jobs += [("m%02d" % k, *m) for k, m in enumerate(mutants, 1)]
     with ThreadPoolExecutor(max_workers=4) as ex:
-        results = list(ex.map(lambda m: _run_pins(m[0], m[1], m[2], str(tmp_path)), MUTANTS))
-    survivors = [(name, out) for name, rc, out in results if rc != 1]
+        results = list(ex.map(lambda j: run(*j, workdir), jobs))
+    name, rc, out = results[0]
+    assert rc == 0, ("the unchanged copy fails its pins", out)
     # pytest exits 1 when a test failed; anything else (0 = all passed,
     # 2+ = the run itself broke) means the pins did not catch the slip
+    survivors = [(name, out) for name, rc, out in results[1:] if rc != 1]
     assert not survivors, survivors
+
+
+def test_every_svi_mutant_fails_a_pin(tmp_path):
+    oracle.build(force=False)
+    _check(_run_svi_pins, SVI_MUTANTS, str(tmp_path))
+
+
+def test_every_mutant_fails_a_pin(tmp_path):
+    _check(_run_pins, MUTANTS, str(tmp_path))
