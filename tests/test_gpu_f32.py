@@ -48,7 +48,13 @@ def check(fv, model, P, fs, K, T, r, q, flag):
         np.ascontiguousarray(flag, dtype=np.int8)).to("cuda"), q=d32(A[5]))
     sig = sig.cpu().numpy().astype(np.float64)
     st = st.cpu().numpy()
-    D = [a.astype(np.float64) for a in A]
+    return compare_f32(model, [a.astype(np.float64) for a in A], flag, sig, st)
+
+
+def compare_f32(model, D, flag, sig, st):
+    """The contract above for binary32 inputs D (promoted exactly to float64:
+    price, S/F, K, T, r, q), flags, and the GPU's sigma (as float64) and
+    status; returns (quotes solved by both, largest error / tolerance)."""
     so, sto = oracle.implied_vol(model, *D, flag)
     dom = (sto == 0) & (st == 5)
     if dom.any():

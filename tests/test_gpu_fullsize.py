@@ -7,8 +7,11 @@ oracle computes one by one, plus properties checked on every output.
     grid) and 3,000 injected quotes against the oracle; over all quotes, the
     status conventions, every injected quote flagged, every clean quote
     solved.
-  * 2,000 ragged Black-76 chains (about 8.4M quotes) in one launch: a sample
-    against the oracle, and every quote solved.
+  * 2,000 ragged Black-76 chains (about 8.4M quotes) in one launch, both
+    solvers: a sample against the oracle, and every quote solved.
+  * The binary32 Halley path on the 10M batch rounded to float32, sampled.
+  * The 1M differentiation workload's forward with the Greeks fused in:
+    sampled Greeks against the oracle's.
   * The 1,000,000-quote differentiation workload through autograd: sampled
     gradients against the oracle's implicit-function gradient.
   * SVI calibration on 500 chains (2.08M quotes): the first 20 losses and
@@ -110,6 +113,71 @@ def test_ragged_chains_full_sampled(fv):
     # price: solved everywhere
     assert (st == 0).mean() > 0.9999
     assert np.all(np.isfinite(sig[st == 0]))
+
+
+def test_ragged_chains_full_halley_sampled(fv):
+    ch = W.b76_chains(2000, seed=3)
+    flat = ch.flatten()
+    P = oracle.price("black76", flat.fs, flat.K, flat.T, flat.r, 0.0, flat.sigma_true, flat.flag)
+    sig, st = fv.implied_vol_chains(dev(ch.chain_mat_off, torch.int64),
+                                    dev(ch.mat_quote_off, torch.int64), dev(ch.F), dev(ch.r),
+                                    dev(ch.T), dev(P), dev(ch.K), dev(ch.flag, torch.int8),
+                                    solver="halley")
+    torch.cuda.synchronize()
+    sig, st = sig.cpu().numpy(), st.cpu().numpy()
+    idx = _sample(flat.n, np.random.default_rng(14))
+    res = compare_iv("black76", "halley", P[idx], flat.fs[idx], flat.K[idx], flat.T[idx],
+                     flat.r[idx], 0.0, flat.flag[idx], sig[idx], st[idx])
+    assert len(res["status_bad"]) == 0 and len(res["value_bad"]) == 0 and len(res["nan_bad"]) == 0
+    assert (st == 0).mean() > 0.9999
+
+
+def test_fused_greeks_1m_sampled(fv):
+    """The differentiation workload's forward with the Greeks fused in, at
+    its full size: sampled Greeks at the solved sigma against the oracle's
+    Greeks at the oracle's sigma (the Greeks' tolerance plus their change
+    over the sigma error the parity tolerance allows)."""
+    wl = W.bsm_diff(1_000_000, seed=4)
+    P = assemble_prices(wl)
+    sig, st, gk = fv.implied_vol("bsm", dev(P), dev(wl.fs), dev(wl.K), dev(wl.T), dev(wl.r),
+                                 flag=dev(wl.flag, torch.int8), q=dev(wl.q), greeks=True)
+    torch.cuda.synchronize()
+    sig, st = sig.cpu().numpy(), st.cpu().numpy()
+    idx = _sample(wl.n, np.random.default_rng(15))
+    ok = st[idx] == 0
+    idx = idx[ok]
+    so, sto = oracle.implied_vol("bsm", P[idx], wl.fs[idx], wl.K[idx], wl.T[idx], wl.r[idx],
+                                 wl.q[idx], wl.flag[idx])
+    assert np.all(sto == 0)
+    g_at_gpu = oracle.greeks("bsm", wl.fs[idx], wl.K[idx], wl.T[idx], wl.r[idx], wl.q[idx],
+                             sig[idx], wl.flag[idx])
+    for name in ("delta", "gamma", "vega", "theta", "rho"):
+        a = gk[name].cpu().numpy()[idx]
+        b = g_at_gpu[name]
+        scale = np.abs(b) + 1e-9 * np.max(np.abs(b))
+        rel = np.abs(a - b) / scale
+        assert np.quantile(rel, 0.999) < 1e-9 and np.max(rel) < 1e-6, (name, rel.max())
+
+
+def test_binary32_10m_sampled(fv, wide10m):
+    """The binary32 Halley path on the 10M wide workload rounded to float32,
+    sampled against the oracle on the same binary32 inputs."""
+    from test_gpu_f32 import compare_f32
+    wl, P = wide10m
+    A = [np.ascontiguousarray(x, dtype=np.float32) for x in (P, wl.fs, wl.K, wl.T, wl.r, wl.q)]
+    t32 = [torch.from_numpy(a).to("cuda") for a in A]
+    sig, st = fv.implied_vol_f32("bsm", *t32[:5], flag=dev(wl.flag, torch.int8), q=t32[5])
+    torch.cuda.synchronize()
+    sig, st = sig.cpu().numpy().astype(np.float64), st.cpu().numpy()
+    inj = wl.kind != W.KIND_CLEAN
+    rng = np.random.default_rng(16)
+    idx = _sample(wl.n, rng, extra=rng.choice(np.where(inj)[0], 3000, replace=False))
+    n_ok, worst = compare_f32("bsm", [a[idx].astype(np.float64) for a in A], wl.flag[idx],
+                              sig[idx], st[idx])
+    # float32 rounding puts more deep in-the-money prices onto their bounds
+    # and leaves normalised prices below 2^-100 to the binary64 path (both
+    # checked quote by quote above); about 91% of the clean sample is solved
+    assert n_ok > 0.85 * (~inj[idx]).sum() and worst <= 1.0
 
 
 def test_differentiation_1m_sampled(fv):
