@@ -256,16 +256,34 @@ int fv_lbr_trace(int model, const fv_quotes *q, uint32_t *path_out, void *stream
  * the Halley families the workgroup's queue of unconverged quotes (24 bytes
  * per quote, 16 for binary32) must fit in 64 KiB of LDS
  * (FV_E_INVALID_ARG otherwise; the shape in force is kept).
- * fv_get_launch reads the current shape.  The shape applies as set to
+ * fv_get_launch reads the configured shape.  The shape applies as set to
  * batches large enough to fill the device; a batch that would give fewer
  * than 8 waves per SIMD (32 per compute unit) runs with fewer quotes per
  * thread (halved until it has them, or one per thread), and with fewer than
  * one workgroup per compute unit also with 64-thread workgroups.  No result
  * depends on the
- * shape.  fv_autotune times the candidate shapes (block 64..512, 1..8 quotes
- * per thread) of one kernel family on the given stream with synthetic
- * in-range quotes of size n_hint (the library allocates and frees scratch
- * for this call only -- it is not graph-capturable) and keeps the fastest. */
+ * shape.
+ *
+ * Autotuner: fv_autotune(kernel, model, n_hint, stream) times the candidate
+ * shapes (block 64..512, 1..8 quotes per thread, within the LDS limit above)
+ * of one kernel family on `stream` with synthetic in-range quotes, on a
+ * batch of min(n_hint, 2^24) quotes (whole groups of 2,048), and keeps the
+ * fastest for that family, model and the size class of n_hint -- the
+ * classes are n < 2^14, [2^14, 2^16), [2^16, 2^18), [2^18, 2^20),
+ * [2^20, 2^22), [2^22, 2^24) and n >= 2^24 (the ragged family is always
+ * Black-76).  From then on a launch whose batch falls in a tuned class uses
+ * the tuned shape as measured; untuned classes keep the configured shape and
+ * its narrowing.  fv_autotune allocates and frees scratch for this call only
+ * and synchronises the stream: it is not graph-capturable.  fv_set_launch
+ * clears the family's tuned classes (an explicit shape wins).
+ * fv_launch_shape reports the shape a launch of n >= 1 quotes would use.
+ * fv_tuning_save writes every tuned class to a JSON file stamped with the
+ * device's architecture name (hipDeviceProp_t::gcnArchName);
+ * fv_tuning_load replaces the tuned classes with a file's, validating every
+ * entry first (FV_E_INVALID_ARG for an unreadable or malformed file, nothing
+ * applied) and refusing a file written on another architecture
+ * (FV_E_UNSUPPORTED); fv_tuning_reset forgets every tuned class.  These
+ * calls change process-wide state (see the threading note above). */
 enum fv_kernel {
     FV_KERNEL_PRICE = 0,
     FV_KERNEL_IV_LBR = 1,
@@ -279,6 +297,10 @@ enum fv_kernel {
 int fv_set_launch(int kernel, int block, int quotes_per_thread);
 int fv_get_launch(int kernel, int *block, int *quotes_per_thread);
 int fv_autotune(int kernel, int model, int64_t n_hint, void *stream);
+int fv_launch_shape(int kernel, int model, int64_t n, int *block, int *quotes_per_thread);
+int fv_tuning_reset(void);
+int fv_tuning_save(const char *path);
+int fv_tuning_load(const char *path);
 
 /* Human-readable reason of the last failed call on this host thread. */
 const char *fv_last_error(void);

@@ -67,7 +67,8 @@ class FvSviProblem(ctypes.Structure):
 
 EXPORTS = ["fv_price", "fv_implied_vol", "fv_implied_vol_f32", "fv_greeks", "fv_implied_vol_backward", "fv_price_backward",
            "fv_implied_vol_chains", "fv_normalised_black", "fv_lbr_trace", "fv_set_launch", "fv_get_launch",
-           "fv_autotune", "fv_svi_adam_step", "fv_svi_vols", "fv_last_error", "fv_version"]
+           "fv_autotune", "fv_launch_shape", "fv_tuning_reset", "fv_tuning_save", "fv_tuning_load",
+           "fv_svi_adam_step", "fv_svi_vols", "fv_last_error", "fv_version"]
 
 _lib = None
 
@@ -102,6 +103,10 @@ def load():
     lib.fv_set_launch.argtypes = [I, I, I]
     lib.fv_get_launch.argtypes = [I, P(I), P(I)]
     lib.fv_autotune.argtypes = [I, I, I64, V]
+    lib.fv_launch_shape.argtypes = [I, I, I64, P(I), P(I)]
+    lib.fv_tuning_reset.argtypes = []
+    lib.fv_tuning_save.argtypes = [ctypes.c_char_p]
+    lib.fv_tuning_load.argtypes = [ctypes.c_char_p]
     lib.fv_last_error.argtypes = []
     lib.fv_version.argtypes = []
     for name in EXPORTS:

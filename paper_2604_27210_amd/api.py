@@ -8,6 +8,7 @@ here computes: a missing or unloadable library raises, there is no fallback.
 from __future__ import annotations
 
 import ctypes
+import os
 from typing import Optional
 
 import torch
@@ -289,10 +290,49 @@ def get_launch(kernel):
 
 
 def autotune(kernel, model="bsm", n_hint: int = 1 << 22, stream=None):
+    """Time the launch shapes of one kernel family on `n_hint` synthetic
+    quotes and keep the fastest for that model and size class; returns it."""
     k = N.KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     N.check(N.load().fv_autotune(k, _model(model), int(n_hint),
                                  ctypes.c_void_p(_stream_ptr(stream))), "fv_autotune")
-    return get_launch(k)
+    return launch_shape(k, model, max(1, int(n_hint)))
+
+
+# one batch size per size class of the tuning table (2^12 .. 2^24)
+TUNING_SIZES = (1 << 12, 1 << 15, 1 << 17, 1 << 19, 1 << 21, 1 << 23, 1 << 24)
+
+
+def autotune_all(kernels=None, models=("bsm",), sizes=TUNING_SIZES, stream=None) -> dict:
+    """fv_autotune over kernel families x models x sizes; returns
+    {(kernel, model, size): (block, quotes_per_thread)}."""
+    kernels = kernels or [k for k in N.KERNELS]
+    out = {}
+    for kern in kernels:
+        for model in (("black76",) if kern == "chains" else models):
+            for n in sizes:
+                out[(kern, model, n)] = autotune(kern, model, n, stream)
+    return out
+
+
+def launch_shape(kernel, model, n: int):
+    """(block, quotes per thread) a launch of n quotes would use."""
+    k = N.KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    b, q = ctypes.c_int(), ctypes.c_int()
+    N.check(N.load().fv_launch_shape(k, _model(model), int(n), ctypes.byref(b), ctypes.byref(q)),
+            "fv_launch_shape")
+    return b.value, q.value
+
+
+def save_tuning(path) -> None:
+    N.check(N.load().fv_tuning_save(os.fsencode(path)), "fv_tuning_save")
+
+
+def load_tuning(path) -> None:
+    N.check(N.load().fv_tuning_load(os.fsencode(path)), "fv_tuning_load")
+
+
+def reset_tuning() -> None:
+    N.check(N.load().fv_tuning_reset(), "fv_tuning_reset")
 
 
 def version() -> int:

@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -773,12 +775,40 @@ int device_cus() {
   return cus;
 }
 
-// The configured shape of `kernel`, narrowed for a batch of n quotes too
-// small to keep every SIMD busy: quotes per thread halve until the launch
-// has at least 8 waves per SIMD (32 per CU; fewer, longer waves leave SIMDs
-// idle at the end), and the workgroup drops to one wave if there is still
-// less than one workgroup per CU.  Results never depend on the shape.
-LaunchShape shape_for(int kernel, int64_t n) {
+// ---------------------------------------------------------- tuning table
+// fv_autotune's results per (kernel family, model, size class of the batch);
+// a launch uses the entry of its class, as measured, when there is one.
+constexpr int kModels = 3;
+constexpr int kBuckets = 7;
+struct Tuned {
+  int block, qpt;  // block == 0: not tuned
+  float ms;        // the winning candidate's time when it was measured
+};
+Tuned g_tuned[FV_KERNEL_COUNT][kModels][kBuckets];
+// while fv_autotune times a candidate, launches of that family take it as is
+int g_tuning_kernel = -1;
+LaunchShape g_tuning_shape = {0, 0};
+
+// Size class of a batch of n >= 1 quotes: 0 below 2^14, then one class per
+// factor of 4 ([2^14, 2^16) is 1, ...), 6 from 2^24 up.
+int bucket_of(int64_t n) {
+  int lg = 0;
+  while (lg < 62 && ((int64_t)1 << (lg + 1)) <= n) ++lg;
+  if (lg < 14) return 0;
+  return std::min(kBuckets - 1, (lg - 14) / 2 + 1);
+}
+
+// The shape a launch of n quotes of `kernel` under `model` uses: a tuned
+// entry of its size class if there is one, else the configured shape,
+// narrowed for a batch too small to keep every SIMD busy: quotes per thread
+// halve until the launch has at least 8 waves per SIMD (32 per CU; fewer,
+// longer waves leave SIMDs idle at the end), and the workgroup drops to one
+// wave if there is still less than one workgroup per CU.  Results never
+// depend on the shape.
+LaunchShape shape_for(int kernel, int model, int64_t n) {
+  if (kernel == g_tuning_kernel) return g_tuning_shape;
+  const Tuned& t = g_tuned[kernel][model][bucket_of(n > 0 ? n : 1)];
+  if (t.block) return LaunchShape{t.block, t.qpt};
   LaunchShape sh = g_shape[kernel];
   const int64_t cus = device_cus();
   auto waves = [n](const LaunchShape& t) {
@@ -787,6 +817,84 @@ LaunchShape shape_for(int kernel, int64_t n) {
   while (sh.qpt > 1 && waves(sh) < 32 * cus) sh.qpt = (sh.qpt + 1) / 2;
   if ((n + sh.block - 1) / sh.block < cus) sh.block = 64;
   return sh;
+}
+
+// Architecture name of the current device (hipDeviceProp_t::gcnArchName,
+// e.g. "gfx950:sramecc+:xnack-"), the key a tuning file is valid for.
+int device_arch(std::string* out) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(FV_E_HIP, "no HIP device to read the architecture of");
+  *out = prop.gcnArchName;
+  return FV_OK;
+}
+
+// Value of the integer field "key" inside [b, e) of a tuning file's text.
+bool int_field(const std::string& t, size_t b, size_t e, const char* key, long* v) {
+  const std::string k = std::string("\"") + key + "\"";
+  const size_t at = t.find(k, b);
+  if (at == std::string::npos || at >= e) return false;
+  size_t i = at + k.size();
+  while (i < e && (t[i] == ' ' || t[i] == ':')) ++i;
+  char* endp = nullptr;
+  const long x = strtol(t.c_str() + i, &endp, 10);
+  if (endp == t.c_str() + i) return false;
+  *v = x;
+  return true;
+}
+
+// Reads a tuning file written by fv_tuning_save into `table` (all entries
+// validated; nothing is returned on any error) and its "arch" string.
+int parse_tuning(const char* path, std::string* text, std::string* arch,
+                 Tuned (*table)[kModels][kBuckets]) {
+  FILE* f = fopen(path, "r");
+  if (!f) return fail(FV_E_INVALID_ARG, std::string("cannot read ") + path);
+  char buf[4096];
+  size_t got;
+  text->clear();
+  while ((got = fread(buf, 1, sizeof(buf), f)) > 0 && text->size() < (1u << 20))
+    text->append(buf, got);
+  fclose(f);
+  const std::string& t = *text;
+  auto bad = [&](const char* why) {
+    return fail(FV_E_INVALID_ARG, std::string("tuning file ") + path + ": " + why);
+  };
+  if (t.find("\"format\": \"fastvol-tuning\"") == std::string::npos) return bad("not a tuning file");
+  long version = 0;
+  if (!int_field(t, 0, t.size(), "version", &version) || version != 1)
+    return bad("unsupported version");
+  const size_t a = t.find("\"arch\": \"");
+  if (a == std::string::npos) return bad("no arch");
+  const size_t a0 = a + 9, a1 = t.find('"', a0);
+  if (a1 == std::string::npos || a1 == a0) return bad("no arch");
+  *arch = t.substr(a0, a1 - a0);
+  size_t pos = t.find("\"entries\"");
+  if (pos == std::string::npos) return bad("no entries");
+  memset(table, 0, sizeof(Tuned) * FV_KERNEL_COUNT * kModels * kBuckets);
+  while ((pos = t.find('{', pos)) != std::string::npos) {
+    const size_t end = t.find('}', pos);
+    if (end == std::string::npos) return bad("unterminated entry");
+    long k, m, b, blk, qq;
+    if (!int_field(t, pos, end, "kernel", &k) || !int_field(t, pos, end, "model", &m) ||
+        !int_field(t, pos, end, "bucket", &b) || !int_field(t, pos, end, "block", &blk) ||
+        !int_field(t, pos, end, "qpt", &qq))
+      return bad("entry without kernel, model, bucket, block or qpt");
+    if (k < 0 || k >= FV_KERNEL_COUNT || m < 0 || m >= kModels || b < 0 || b >= kBuckets)
+      return bad("entry out of range");
+    if (!valid_shape((int)blk, (int)qq) || queue_bytes((int)k, (int)blk, (int)qq) > kMaxQueueBytes)
+      return bad("invalid launch shape");
+    float ms = 0.0f;
+    const size_t mk = t.find("\"ms\"", pos);
+    if (mk != std::string::npos && mk < end) {
+      size_t i = mk + 4;
+      while (i < end && (t[i] == ' ' || t[i] == ':')) ++i;
+      ms = (float)strtod(t.c_str() + i, nullptr);
+    }
+    table[k][m][b] = Tuned{(int)blk, (int)qq, ms};
+    pos = end + 1;
+  }
+  return FV_OK;
 }
 
 }  // namespace
@@ -805,6 +913,8 @@ int fv_set_launch(int kernel, int block, int qpt) {
     return fail(FV_E_INVALID_ARG, "launch shape: Halley queue above 64 KiB of LDS");
   g_shape[kernel].block = block;
   g_shape[kernel].qpt = qpt;
+  // an explicit shape wins over the family's tuned entries
+  memset(g_tuned[kernel], 0, sizeof(g_tuned[kernel]));
   return FV_OK;
 }
 
@@ -821,7 +931,7 @@ int fv_price(int model, const fv_quotes* q, fv_arg sigma, double* price_out, voi
   if (rc) return rc;
   if (q->n == 0) return FV_OK;
   if (!price_out) return fail(FV_E_INVALID_ARG, "price_out is NULL");
-  const LaunchShape sh = shape_for(FV_KERNEL_PRICE, q->n);
+  const LaunchShape sh = shape_for(FV_KERNEL_PRICE, model, q->n);
   const KQuotes k = to_k(q);
   hipStream_t s = (hipStream_t)stream;
   const dim3 grid = grid_for(q->n, sh), block(sh.block);
@@ -850,7 +960,7 @@ int fv_implied_vol(int model, int solver, const fv_quotes* q, double* sigma_out,
   const KQuotes k = to_k(q);
   hipStream_t s = (hipStream_t)stream;
   if (solver == FV_SOLVER_LBR) {
-    const LaunchShape sh = shape_for(FV_KERNEL_IV_LBR, q->n);
+    const LaunchShape sh = shape_for(FV_KERNEL_IV_LBR, model, q->n);
     const dim3 grid = grid_for(q->n, sh), block(sh.block);
 #define FV_LBR(M, G) k_iv_lbr<M, G><<<grid, block, 0, s>>>(k, sigma_out, status_out, g, sh.qpt)
     switch (model * 2 + (g.any ? 1 : 0)) {
@@ -864,7 +974,7 @@ int fv_implied_vol(int model, int solver, const fv_quotes* q, double* sigma_out,
 #undef FV_LBR
     return launched("fv_implied_vol(LBR)");
   }
-  const LaunchShape sh = shape_for(FV_KERNEL_IV_HALLEY, q->n);
+  const LaunchShape sh = shape_for(FV_KERNEL_IV_HALLEY, model, q->n);
   const dim3 grid = grid_for(q->n, sh), block(sh.block);
   const size_t lds = sizeof(Pending) * (size_t)sh.block * sh.qpt;
 #define FV_HAL(M, G) k_iv_halley<M, G><<<grid, block, lds, s>>>(k, sigma_out, status_out, g, sh.qpt)
@@ -901,7 +1011,7 @@ int fv_implied_vol_f32(int model, const fv_quotes_f32* q, float* sigma_out,
   k.q = q->q;
   k.flag = q->flag;
   k.flag_value = q->flag_value;
-  const LaunchShape sh = shape_for(FV_KERNEL_IV_HALLEY_F32, q->n);
+  const LaunchShape sh = shape_for(FV_KERNEL_IV_HALLEY_F32, model, q->n);
   const dim3 grid = grid_for(q->n, sh), block(sh.block);
   const size_t lds = sizeof(Pending32) * (size_t)sh.block * sh.qpt;
   hipStream_t s = (hipStream_t)stream;
@@ -922,7 +1032,7 @@ int fv_greeks(int model, const fv_quotes* q, fv_arg sigma, double* delta, double
   g.p[0] = delta; g.p[1] = gamma; g.p[2] = vega; g.p[3] = theta; g.p[4] = rho;
   g.any = 1;
   if (!delta && !gamma && !vega && !theta && !rho) return FV_OK;
-  const LaunchShape sh = shape_for(FV_KERNEL_GREEKS, q->n);
+  const LaunchShape sh = shape_for(FV_KERNEL_GREEKS, model, q->n);
   const KQuotes k = to_k(q);
   hipStream_t s = (hipStream_t)stream;
   const dim3 grid = grid_for(q->n, sh), block(sh.block);
@@ -943,7 +1053,7 @@ int fv_implied_vol_backward(int model, const fv_quotes* q, const double* sigma,
   if (!sigma || !grad_sigma) return fail(FV_E_INVALID_ARG, "sigma or grad_sigma is NULL");
   BwdOut o;
   o.p[0] = g_price; o.p[1] = g_fs; o.p[2] = g_K; o.p[3] = g_T; o.p[4] = g_r; o.p[5] = g_q;
-  const LaunchShape sh = shape_for(FV_KERNEL_BACKWARD, q->n);
+  const LaunchShape sh = shape_for(FV_KERNEL_BACKWARD, model, q->n);
   const KQuotes k = to_k(q);
   hipStream_t s = (hipStream_t)stream;
   const dim3 grid = grid_for(q->n, sh), block(sh.block);
@@ -964,7 +1074,7 @@ int fv_price_backward(int model, const fv_quotes* q, fv_arg sigma, const double*
   if (!grad_price) return fail(FV_E_INVALID_ARG, "grad_price is NULL");
   BwdOut o;
   o.p[0] = g_fs; o.p[1] = g_K; o.p[2] = g_T; o.p[3] = g_r; o.p[4] = g_q; o.p[5] = g_sigma;
-  const LaunchShape sh = shape_for(FV_KERNEL_BACKWARD, q->n);
+  const LaunchShape sh = shape_for(FV_KERNEL_BACKWARD, model, q->n);
   const KQuotes k = to_k(q);
   hipStream_t s = (hipStream_t)stream;
   const dim3 grid = grid_for(q->n, sh), block(sh.block);
@@ -981,7 +1091,7 @@ int fv_lbr_trace(int model, const fv_quotes* q, uint32_t* path_out, void* stream
   if (rc) return rc;
   if (q->n == 0) return FV_OK;
   if (!path_out) return fail(FV_E_INVALID_ARG, "path_out is NULL");
-  const LaunchShape sh = shape_for(FV_KERNEL_IV_LBR, q->n);
+  const LaunchShape sh = shape_for(FV_KERNEL_IV_LBR, model, q->n);
   const KQuotes k = to_k(q);
   hipStream_t s = (hipStream_t)stream;
   const dim3 grid = grid_for(q->n, sh), block(sh.block);
@@ -1018,7 +1128,7 @@ int fv_implied_vol_chains(int solver, const fv_chains* c, double* sigma_out,
   k.price = c->price;
   k.K = c->K;
   k.flag = c->flag;
-  const LaunchShape sh = shape_for(FV_KERNEL_CHAINS, k.n);
+  const LaunchShape sh = shape_for(FV_KERNEL_CHAINS, FV_MODEL_BLACK76, k.n);
   const int64_t chunk = (int64_t)sh.block * sh.qpt;
   const int64_t n_chunks = (k.n + chunk - 1) / chunk;
   // One workgroup per chunk: the hardware hands chunks to CUs as waves
@@ -1050,10 +1160,14 @@ int fv_autotune(int kernel, int model, int64_t n_hint, void* stream) {
   if (model < FV_MODEL_BLACK76 || model > FV_MODEL_BSM)
     return fail(FV_E_INVALID_ARG, "model out of range");
   if (n_hint < 0) return fail(FV_E_INVALID_ARG, "n_hint < 0");
-  // time on a batch large enough to fill the device, at most n_hint quotes
-  int64_t n = std::max<int64_t>(std::min<int64_t>(n_hint, 1 << 24), 1 << 18);
+  // time on a batch of the requested size class: n_hint quotes, at most
+  // 2^24, rounded down to whole synthetic chains (at least one group of 8)
   const int per_mat = 256, mats = 8;
-  n = (n / (per_mat * mats)) * (per_mat * mats);
+  int64_t n = std::min<int64_t>(n_hint, 1 << 24);
+  n = std::max<int64_t>((n / (per_mat * mats)) * (per_mat * mats), per_mat * mats);
+  // the chain kernel only runs Black-76
+  const int tuned_model = kernel == FV_KERNEL_CHAINS ? FV_MODEL_BLACK76 : model;
+  const int bucket = bucket_of(n_hint > 0 ? n_hint : 1);
   const int64_t n_mat = n / per_mat, n_chains = n_mat / mats;
   hipStream_t s = (hipStream_t)stream;
 
@@ -1120,8 +1234,6 @@ int fv_autotune(int kernel, int model, int64_t n_hint, void* stream) {
   cs.K = K;
   cs.flag = flag;
 
-  const LaunchShape saved_price = g_shape[FV_KERNEL_PRICE];
-  g_shape[FV_KERNEL_PRICE] = {256, 1};
   int rc = FV_OK;
   // input prices: the model's own prices of sigma (the chain kernel reads
   // Black-76 prices of the chain forwards)
@@ -1136,7 +1248,6 @@ int fv_autotune(int kernel, int model, int64_t n_hint, void* stream) {
   } else {
     rc = fv_price(model, &qs, sa, P, stream);
   }
-  g_shape[FV_KERNEL_PRICE] = saved_price;
   fv_quotes_f32 q32;
   memset(&q32, 0, sizeof(q32));
   if (f32) {
@@ -1168,13 +1279,14 @@ int fv_autotune(int kernel, int model, int64_t n_hint, void* stream) {
   };
   const int blocks[] = {64, 128, 256, 512};
   const int qpts[] = {1, 2, 4, 8};
-  LaunchShape best = g_shape[kernel];
+  LaunchShape best = {0, 0};
   float best_ms = 1e30f;
   for (int b : blocks) {
     for (int qq : qpts) {
       if (rc != FV_OK) break;
       if (queue_bytes(kernel, b, qq) > kMaxQueueBytes) continue;
-      g_shape[kernel] = {b, qq};
+      g_tuning_kernel = kernel;
+      g_tuning_shape = LaunchShape{b, qq};
       rc = run();  // warm-up
       float tot = 0.0f, mn = 1e30f;
       for (int rep = 0; rep < 3 && rc == FV_OK; ++rep) {
@@ -1194,12 +1306,73 @@ int fv_autotune(int kernel, int model, int64_t n_hint, void* stream) {
       }
     }
   }
-  g_shape[kernel] = best;
+  g_tuning_kernel = -1;
+  if (rc == FV_OK && best.block)
+    g_tuned[kernel][tuned_model][bucket] = Tuned{best.block, best.qpt, best_ms};
   hipStreamSynchronize(s);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   release();
   return rc;
+}
+
+int fv_launch_shape(int kernel, int model, int64_t n, int* block, int* qpt) {
+  if (kernel < 0 || kernel >= FV_KERNEL_COUNT || !block || !qpt)
+    return fail(FV_E_INVALID_ARG, "kernel id or NULL output");
+  if (model < FV_MODEL_BLACK76 || model > FV_MODEL_BSM)
+    return fail(FV_E_INVALID_ARG, "model out of range");
+  if (n < 1) return fail(FV_E_INVALID_ARG, "n < 1");
+  const LaunchShape sh =
+      shape_for(kernel, kernel == FV_KERNEL_CHAINS ? FV_MODEL_BLACK76 : model, n);
+  *block = sh.block;
+  *qpt = sh.qpt;
+  return FV_OK;
+}
+
+int fv_tuning_reset(void) {
+  memset(g_tuned, 0, sizeof(g_tuned));
+  return FV_OK;
+}
+
+int fv_tuning_save(const char* path) {
+  if (!path) return fail(FV_E_INVALID_ARG, "path is NULL");
+  std::string arch;
+  const int rc = device_arch(&arch);
+  if (rc) return rc;
+  FILE* f = fopen(path, "w");
+  if (!f) return fail(FV_E_INVALID_ARG, std::string("cannot write ") + path);
+  fprintf(f, "{\"format\": \"fastvol-tuning\", \"version\": 1, \"arch\": \"%s\", \"entries\": [",
+          arch.c_str());
+  bool first = true;
+  for (int k = 0; k < FV_KERNEL_COUNT; ++k)
+    for (int m = 0; m < kModels; ++m)
+      for (int b = 0; b < kBuckets; ++b) {
+        const Tuned& t = g_tuned[k][m][b];
+        if (!t.block) continue;
+        fprintf(f, "%s\n  {\"kernel\": %d, \"model\": %d, \"bucket\": %d, \"block\": %d, "
+                   "\"qpt\": %d, \"ms\": %.6g}",
+                first ? "" : ",", k, m, b, t.block, t.qpt, (double)t.ms);
+        first = false;
+      }
+  fprintf(f, "\n]}\n");
+  const bool ok = !ferror(f);
+  fclose(f);
+  return ok ? FV_OK : fail(FV_E_INVALID_ARG, std::string("write failed: ") + path);
+}
+
+int fv_tuning_load(const char* path) {
+  if (!path) return fail(FV_E_INVALID_ARG, "path is NULL");
+  std::string text, arch;
+  Tuned table[FV_KERNEL_COUNT][kModels][kBuckets];
+  int rc = parse_tuning(path, &text, &arch, table);
+  if (rc) return rc;
+  std::string here;
+  rc = device_arch(&here);
+  if (rc) return rc;
+  if (arch != here)
+    return fail(FV_E_UNSUPPORTED, "tuning file is for " + arch + ", this device is " + here);
+  memcpy(g_tuned, table, sizeof(g_tuned));
+  return FV_OK;
 }
 
 }  // extern "C"

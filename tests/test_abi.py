@@ -100,3 +100,41 @@ def test_library_is_gfx950_code():
         pytest.skip("not built")
     blob = open(N.LIB_PATH, "rb").read()
     assert b"gfx950" in blob
+
+
+def test_tuning_file_validation_and_shape_query(lib, tmp_path):
+    """Malformed tuning files are refused before any device is touched, and
+    the shape query reports the configured shape narrowed for small batches."""
+    from paper_2604_27210_amd import _native as N
+    bad = {
+        "empty": "",
+        "not ours": "{}",
+        "version": '{"format": "fastvol-tuning", "version": 2, "arch": "x", "entries": []}',
+        "bucket": '{"format": "fastvol-tuning", "version": 1, "arch": "x", "entries": '
+                  '[{"kernel": 1, "model": 2, "bucket": 9, "block": 128, "qpt": 1}]}',
+        "lds": '{"format": "fastvol-tuning", "version": 1, "arch": "x", "entries": '
+               '[{"kernel": 2, "model": 2, "bucket": 3, "block": 512, "qpt": 16}]}',
+        "block": '{"format": "fastvol-tuning", "version": 1, "arch": "x", "entries": '
+                 '[{"kernel": 1, "model": 2, "bucket": 3, "block": 96, "qpt": 1}]}',
+        "field": '{"format": "fastvol-tuning", "version": 1, "arch": "x", "entries": '
+                 '[{"kernel": 1, "model": 2, "block": 128, "qpt": 1}]}',
+    }
+    for name, text in bad.items():
+        p = tmp_path / (name + ".json")
+        p.write_text(text)
+        assert lib.fv_tuning_load(str(p).encode()) == N.FV_E_INVALID_ARG, name
+    assert lib.fv_tuning_load(str(tmp_path / "missing.json").encode()) == N.FV_E_INVALID_ARG
+    assert lib.fv_tuning_load(None) == N.FV_E_INVALID_ARG
+    assert lib.fv_tuning_save(None) == N.FV_E_INVALID_ARG
+    assert lib.fv_tuning_reset() == N.FV_OK
+    b, q = ctypes.c_int(), ctypes.c_int()
+    assert lib.fv_launch_shape(1, 2, 0, ctypes.byref(b), ctypes.byref(q)) == N.FV_E_INVALID_ARG
+    assert lib.fv_launch_shape(9, 2, 10, ctypes.byref(b), ctypes.byref(q)) == N.FV_E_INVALID_ARG
+    gb, gq = ctypes.c_int(), ctypes.c_int()
+    assert lib.fv_get_launch(1, ctypes.byref(gb), ctypes.byref(gq)) == N.FV_OK
+    # a batch far larger than the device: the configured shape as is
+    assert lib.fv_launch_shape(1, 2, 1 << 30, ctypes.byref(b), ctypes.byref(q)) == N.FV_OK
+    assert (b.value, q.value) == (gb.value, gq.value)
+    # one quote: one-wave workgroups, one quote per thread
+    assert lib.fv_launch_shape(1, 2, 1, ctypes.byref(b), ctypes.byref(q)) == N.FV_OK
+    assert (b.value, q.value) == (64, 1)

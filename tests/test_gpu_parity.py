@@ -313,22 +313,56 @@ def test_invalid_calls_raise(fv):
         fv.implied_vol("bsm", d, d, d.float(), d, d)
 
 
-def test_autotune_picks_a_valid_shape_and_results_do_not_change(fv):
+def test_autotune_per_size_class_and_tuning_file(fv, tmp_path):
+    """fv_autotune keeps a valid shape per (family, model, size class), the
+    launches of that class use it, per-quote results do not change, and a
+    saved tuning file restores the table after a reset (and only on this
+    architecture)."""
     wl = W.bsm_wide(50_000, seed=21, inject=0.0)
     P = assemble_prices(wl)
     s_ref, st_ref = run_iv(fv, wl, P, "lbr")
-    kernels = ("price", "iv_lbr", "iv_halley", "greeks", "backward", "chains")
+    kernels = ("price", "iv_lbr", "iv_halley", "greeks", "backward", "chains", "iv_halley_f32")
     saved = {k: fv.get_launch(k) for k in kernels}
     try:
-        b, q = fv.autotune("iv_lbr", "bsm", 1 << 20)
-        assert b % 64 == 0 and 64 <= b <= 512 and 1 <= q <= 16
+        fv.reset_tuning()
+        untuned = fv.launch_shape("iv_lbr", "bsm", 50_000)
+        tuned = {}
+        for n in (50_000, 1 << 20):
+            b, q = fv.autotune("iv_lbr", "bsm", n)
+            assert b % 64 == 0 and 64 <= b <= 512 and 1 <= q <= 8
+            tuned[n] = (b, q)
+            # every batch of the same size class launches with it
+            assert fv.launch_shape("iv_lbr", "bsm", n) == (b, q)
+        # another model's class is untouched
+        assert fv.launch_shape("iv_lbr", "black76", 50_000) == untuned
         s, st = run_iv(fv, wl, P, "lbr")
         assert torch.equal(torch.nan_to_num(s, nan=-1.0), torch.nan_to_num(s_ref, nan=-1.0))
         assert torch.equal(st, st_ref)
-        for kern in ("price", "iv_halley", "greeks", "backward", "chains"):
+        for kern in ("price", "iv_halley", "greeks", "backward", "chains", "iv_halley_f32"):
             b, q = fv.autotune(kern, "black76" if kern == "chains" else "bsm", 1 << 19)
-            assert b % 64 == 0 and 1 <= q <= 16
+            assert b % 64 == 0 and 1 <= q <= 8
+        path = tmp_path / "tuning.json"
+        fv.save_tuning(str(path))
+        text = path.read_text()
+        assert '"arch": "gfx950' in text
+        fv.reset_tuning()
+        assert fv.launch_shape("iv_lbr", "bsm", 50_000) == untuned
+        fv.load_tuning(str(path))
+        for n, bq in tuned.items():
+            assert fv.launch_shape("iv_lbr", "bsm", n) == bq
+        # a file written on another architecture is refused, nothing applied
+        other = tmp_path / "other.json"
+        other.write_text(text.replace('"arch": "gfx950', '"arch": "gfx000'))
+        from paper_2604_27210_amd._native import FastvolError
+        with pytest.raises(FastvolError):
+            fv.load_tuning(str(other))
+        for n, bq in tuned.items():
+            assert fv.launch_shape("iv_lbr", "bsm", n) == bq
+        # an explicit shape wins over the tuned classes of its family
+        fv.set_launch("iv_lbr", 256, 1)
+        assert fv.launch_shape("iv_lbr", "bsm", 1 << 20) == (256, 1)
     finally:
+        fv.reset_tuning()
         for k, (b, q) in saved.items():
             fv.set_launch(k, b, q)
 
