@@ -703,11 +703,11 @@ struct LaunchShape {
 // Defaults from timing sweeps on MI355X (the wide-wing 10M-quote batch for
 // the solvers); fv_autotune re-derives them for other shapes of work.
 LaunchShape g_shape[FV_KERNEL_COUNT] = {
-    {256, 1},  // price
+    {256, 2},  // price
     {128, 4},  // IV LBR
     {128, 4},  // IV Halley
     {256, 1},  // Greeks
-    {256, 1},  // backward
+    {128, 4},  // backward
     {128, 8},  // chains
     {128, 4},  // IV Halley, binary32
 };
