@@ -61,8 +61,10 @@ def test_version_and_error_paths(lib):
         assert b"LDS" in lib.fv_last_error()
         assert lib.fv_get_launch(kern, ctypes.byref(b), ctypes.byref(q)) == N.FV_OK
         assert (b.value, q.value) == saved
+    assert lib.fv_get_launch(0, ctypes.byref(b), ctypes.byref(q)) == N.FV_OK
+    saved = (b.value, q.value)
     assert lib.fv_set_launch(0, 512, 16) == N.FV_OK  # no queue: any valid shape
-    assert lib.fv_set_launch(0, 256, 1) == N.FV_OK
+    assert lib.fv_set_launch(0, *saved) == N.FV_OK
     # invalid model / solver / NULL outputs are refused before any launch
     qs = N.FvQuotes(4, N.FvArg(None, 1.0), N.FvArg(None, 100.0), N.FvArg(None, 100.0),
                     N.FvArg(None, 1.0), N.FvArg(None, 0.0), N.FvArg(None, 0.0), None, 1)
