@@ -29,6 +29,8 @@ if ROOT not in sys.path:
 #    VALU instruction = 1 per lane) from SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64
 #    of one launch over the workload with the quotes sorted by LBR path
 #    (``--census``), where no wave executes a branch another lane skipped;
+#  * valu_per_quote: SQ_INSTS_VALU x 64 / quotes of the same sorted launch,
+#    every vector instruction (compares, selects, conversions included);
 #  * fetch/write_bytes_per_quote: FETCH_SIZE and WRITE_SIZE of the timed
 #    launch, each divided by what the counter reads per byte of a plain
 #    1 GiB device copy (``--copy-probe``) and by the quote count.
@@ -37,10 +39,17 @@ if ROOT not in sys.path:
 LBR_PROFILE = {
     "source_sha256": "1e24e0d707b5e9acc6b0fb5df5f355a29f7e10dbea1f9e66bc7c4d4b10fc3f3e",
     "flop_per_quote": 1161.8,
+    "valu_per_quote": 1106.0,
     "fetch_bytes_per_quote": 49.038,
     "write_bytes_per_quote": 9.008,
 }
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+# VALU issue capacity at the nominal clock: 256 CUs x 4 SIMDs x 16 lanes,
+# one lane-instruction per lane per cycle (a wave64 instruction occupies a
+# SIMD for 4 cycles) at 2.4 GHz -- the rate behind the FP64 peak, counted in
+# instructions of any kind instead of FMA-weighted FLOPs
+VALU_LANES = 256 * 4 * 16
+NOMINAL_CLOCK_HZ = 2.4e9
 HBM_PEAK_GBS = 8000.0
 # algorithmic HBM bytes per quote: six float64 inputs + int8 flag in,
 # float64 sigma + uint8 status out
@@ -410,6 +419,10 @@ def main():
         roof = {"bound": "alu", "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
                 "flop_per_quote": LBR_PROFILE["flop_per_quote"],
+                # share of the chip's VALU issue capacity at 2.4 GHz that the
+                # launch's census vector instructions fill
+                "valu_issue_frac": LBR_PROFILE["valu_per_quote"] * a.n /
+                                   (VALU_LANES * NOMINAL_CLOCK_HZ * avg_kernel_s),
                 "kernel_ms_mean": avg_kernel_s * 1e3,
                 "algorithmic_hbm_GBs": BYTES_PER_QUOTE * a.n / avg_kernel_s / 1e9}
     else:
