@@ -160,20 +160,35 @@ __host__ __device__ __attribute__((always_inline)) inline double lbr_initial_gue
     double x, double beta, double bmax, double ln_beta, int* obj, uint32_t* trace) {
   const double ax = -x;  // |x|, x <= 0
   // At the inflection point h = -t, so b(s_c) needs one erfcx and no exp:
-  //   b_c = (b_max/2) (1 - erfcx(sqrt|x|)),  b'(s_c) = b_max/sqrt(2 pi).
-  // (For tiny |x| the difference loses ~log10(1/sqrt|x|) digits; b_c only
-  // selects the region and shapes the guess.)
+  //   b_c = (b_max/2) (1 - erfcx(a)),  b'(s_c) = b_max/sqrt(2 pi),  a = sqrt|x|,
+  // and the lower tangent point is s_l = s_c - b_c/b'(s_c)
+  //   = sqrt2 a - sqrt(pi/2) (1 - erfcx(a)).
+  // Near the money both differences cancel: s_l ~ sqrt(pi/2) |x| while s_c
+  // and the erfcx error are ~sqrt|x| and ~1e-8, so below a = 0.03 both come
+  // from the series erfcx(a) = sum_n (-a)^n / Gamma(n/2 + 1), whose first two
+  // terms cancel exactly in s_l (truncation after a^7: < a^6/24 relative).
   const double sax = sqrt_lo(ax);
   const double sc = kSqrt2 * sax;
+  double om = 1.0 - erfcx_lo(sax);        // 1 - erfcx(a)
+  double sl = sc - kSqrtPiOver2 * om;     // s_l
+  if (sax < 0.03) {
+    constexpr double c3 = 4.0 / (3.0 * kSqrtPi), c5 = 8.0 / (15.0 * kSqrtPi),
+                     c7 = 16.0 / (105.0 * kSqrtPi);
+    // tail = 1 - c3 a + a^2/2 - c5 a^3 + a^4/6 - c7 a^5
+    const double tail =
+        fma(-sax, fma(-sax, fma(-sax, fma(-sax, fma(-sax, c7, 1.0 / 6.0), c5), 0.5), c3), 1.0);
+    om = sax * fma(-sax, tail, kTwoOverSqrtPi);  // 2a/sqrt(pi) - a^2 tail
+    sl = kSqrtPiOver2 * ax * tail;
+  }
   NBlack nc;
-  nc.b = 0.5 * bmax * (1.0 - erfcx_lo(sax));
+  nc.b = 0.5 * bmax * om;
   nc.c = bmax - nc.b;
   nc.bp = kInvSqrt2Pi * bmax;
   nc.form = kFormDifference;
   const bool lower_half = beta < nc.b;
   // the other boundary point on the side of beta
   const double ibc = rcp_lo_safe(nc.bp);  // b' may underflow to 0
-  const double so = lower_half ? fmax(sc - nc.b * ibc, 0.0) : sc + nc.c * ibc;
+  const double so = lower_half ? fmax(sl, 0.0) : sc + nc.c * ibc;
   const NBlack no = normalised_black_t<true>(x, so, bmax);
   const double ibo = rcp_lo_safe(no.bp);
 
@@ -285,7 +300,9 @@ __host__ __device__ __attribute__((always_inline)) inline LbrResult lbr_solve(
   if (trace) *trace |= (uint32_t)(it - 2) << 2;
   res.s = s;
   res.iterations = it;
-  res.converged = !(fabs(ds) > step_tol * s) || it < max_steps;
+  // converged: the loop stopped on the step test (or the last step passed
+  // it) at a finite positive root
+  res.converged = (!(fabs(ds) > step_tol * s) || it < max_steps) && s > 0.0 && __builtin_isfinite(s);
   return res;
 }
 
@@ -363,8 +380,10 @@ __host__ __device__ __attribute__((always_inline)) inline HalleyState halley_sol
 
 __host__ __device__ inline double bisection_solve(double x, double beta, double bmax, double lo,
                                                   double hi, double rel_tol) {
-  if (!(lo > 0.0)) lo = 1e-8;
-  if (!(hi < 1e300)) hi = 50.0;
+  // an end the caller's bracket did not fix: far below any root, and far
+  // above it (b_max - b(s) < b_max 1e-16 once s exceeds ~20 + |x|/10)
+  if (!(lo > 0.0)) lo = 1e-300;
+  if (!(hi < 1e300)) hi = 1e3;
   // geometric midpoints as sqrt(lo) sqrt(hi): lo hi may underflow
   for (int k = 0; k < 200 && hi - lo > rel_tol * hi; ++k) {
     const double mid = sqrt(lo) * sqrt(hi);

@@ -26,6 +26,8 @@ constexpr double kInvSqrt2 = 0.70710678118654752440;
 constexpr double kSqrt2Pi = 2.50662827463100050242;
 constexpr double kInvSqrt2Pi = 0.39894228040143267794;
 constexpr double kSqrtPiOver2 = 1.25331413731550025121;
+constexpr double kSqrtPi = 1.77245385090551602730;
+constexpr double kTwoOverSqrtPi = 1.12837916709551257390;
 constexpr double kLnSqrt2Pi = 0.91893853320467274178;
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kSqrt3 = 1.73205080756887729353;
@@ -373,7 +375,6 @@ __host__ __device__ inline NBlack normalised_black_t(double x, double s, double 
     B = fma(B, y2, kC[i]);
   }
   if (!comp) {
-    constexpr double kSqrtPi = 1.77245385090551602730;
     constexpr double k2BZ = 2.0 * (kB - coef::kErfcxZ0);
     r.ratio = kSqrtPi * t * R1 * R2 * fma(-k2BZ * R1, D, B);
     r.b = r.bp * r.ratio;

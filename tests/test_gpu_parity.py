@@ -398,3 +398,33 @@ def test_scale_invariance(fv):
     s, st = fv.implied_vol("bs", dev(np.array([5.0, 5.0])), dev(np.array([1e-310, 100.0])),
                            dev(np.array([100.0, 1e-310])), 1.0, 0.0, flag="c")
     assert list(host(st)) == [4, 4] and np.all(np.isnan(host(s)))
+
+
+@pytest.mark.parametrize("model", ["black76", "bs", "bsm"])
+def test_fuzz_extreme_ranges(fv, model):
+    """Seeded fuzz beyond the configured workloads: sigma 1e-4..10,
+    T 1e-6..50 years, r -0.1..0.3, q 0..0.3, |z| up to 12, prices of both
+    flags, plus 2% degenerate prices -- both solvers against the oracle."""
+    rng = np.random.default_rng({"black76": 31, "bs": 32, "bsm": 33}[model])
+    n = 40_000
+    S = np.exp(rng.uniform(np.log(1e-3), np.log(1e5), n))
+    T = np.exp(rng.uniform(np.log(1e-6), np.log(50.0), n))
+    r = rng.uniform(-0.1, 0.3, n)
+    q = rng.uniform(0.0, 0.3, n) if model == "bsm" else np.zeros(n)
+    sig = np.exp(rng.uniform(np.log(1e-4), np.log(10.0), n))
+    z = rng.uniform(-12, 12, n)
+    F, D = forward_discount(model, S, T, r, q)
+    K = F * np.exp(-z * sig * np.sqrt(T))
+    flag = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+    P = oracle.price(model, S, K, T, r, q, sig, flag)
+    deg = rng.random(n) < 0.02
+    P[deg] = P[deg] * rng.choice([0.0, -1.0, 1e6], deg.sum())
+    for solver in ("lbr", "halley"):
+        s, st = fv.implied_vol(model, dev(P), dev(S), dev(K), dev(T), dev(r),
+                               flag=dev(flag, torch.int8), q=dev(q) if model == "bsm" else None,
+                               solver=solver)
+        res = compare_iv(model, solver, P, S, K, T, r, q, flag, host(s), host(st))
+        _report("fuzz/%s/%s" % (model, solver), res)
+        assert len(res["status_bad"]) == 0, res["status_bad"][:5]
+        assert len(res["value_bad"]) == 0, (res["value_bad"][:5], res["max_ratio"])
+        assert len(res["nan_bad"]) == 0
