@@ -400,13 +400,11 @@ def test_scale_invariance(fv):
     assert list(host(st)) == [4, 4] and np.all(np.isnan(host(s)))
 
 
-@pytest.mark.parametrize("model", ["black76", "bs", "bsm"])
-def test_fuzz_extreme_ranges(fv, model):
-    """Seeded fuzz beyond the configured workloads: sigma 1e-4..10,
-    T 1e-6..50 years, r -0.1..0.3, q 0..0.3, |z| up to 12, prices of both
-    flags, plus 2% degenerate prices -- both solvers against the oracle."""
+def _fuzz_quotes(model, n=40_000):
+    """Seeded quotes beyond the configured workloads: S over eight decades,
+    sigma 1e-4..10, T 1e-6..50 years, r -0.1..0.3, q 0..0.3 (BSM), strikes
+    at |z| <= 12 standard deviations, both flags."""
     rng = np.random.default_rng({"black76": 31, "bs": 32, "bsm": 33}[model])
-    n = 40_000
     S = np.exp(rng.uniform(np.log(1e-3), np.log(1e5), n))
     T = np.exp(rng.uniform(np.log(1e-6), np.log(50.0), n))
     r = rng.uniform(-0.1, 0.3, n)
@@ -416,6 +414,15 @@ def test_fuzz_extreme_ranges(fv, model):
     F, D = forward_discount(model, S, T, r, q)
     K = F * np.exp(-z * sig * np.sqrt(T))
     flag = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+    return rng, S, K, T, r, q, sig, flag
+
+
+@pytest.mark.parametrize("model", ["black76", "bs", "bsm"])
+def test_fuzz_extreme_ranges(fv, model):
+    """The fuzz quotes' prices, plus 2% degenerate prices -- both solvers
+    against the oracle."""
+    rng, S, K, T, r, q, sig, flag = _fuzz_quotes(model)
+    n = len(S)
     P = oracle.price(model, S, K, T, r, q, sig, flag)
     deg = rng.random(n) < 0.02
     P[deg] = P[deg] * rng.choice([0.0, -1.0, 1e6], deg.sum())
@@ -428,3 +435,66 @@ def test_fuzz_extreme_ranges(fv, model):
         assert len(res["status_bad"]) == 0, res["status_bad"][:5]
         assert len(res["value_bad"]) == 0, (res["value_bad"][:5], res["max_ratio"])
         assert len(res["nan_bad"]) == 0
+
+
+@pytest.mark.parametrize("model", ["black76", "bs", "bsm"])
+def test_fuzz_greeks_and_gradient(fv, model):
+    """Greeks and the implied-volatility gradient at the fuzz quotes' exact
+    roots (the oracle's, rounded to binary64), against the oracle's binary128
+    values.  The bound follows the conditioning of the binary64 arguments:
+    d1 and d2 carry an absolute error of about u (2 + |x| + |(r - q)T| +
+    |rT| + s^2)/s, which a normal density or tail probability at d turns
+    into a relative error of (|d| + 1) times that; theta and dP/dT are sums
+    of terms of both signs, so their bound scales with the sum of the
+    terms' magnitudes instead of the value."""
+    _, S, K, T, r, q, sig, flag = _fuzz_quotes(model)
+    P = oracle.price(model, S, K, T, r, q, sig, flag)
+    so, sto = oracle.implied_vol(model, P, S, K, T, r, q, flag)
+    ok = (sto == 0) & (so > 0)
+    S, K, T, r, q, flag, P, so = (a[ok] for a in (S, K, T, r, q, flag, P, so))
+    F, D = forward_discount(model, S, T, r, q)
+    Fx = S if model == "black76" else F
+    s = so * np.sqrt(T)
+    x = np.log(Fx / K)
+    d1 = x / s + 0.5 * s
+    d2 = d1 - s
+    carry = np.abs((r - q) * T) if model != "black76" else 0.0
+    kappa = 1.0 + (np.abs(d1) + np.abs(d2) + 1.0) * (2.0 + np.abs(x) + carry + np.abs(r * T) + s * s) / s
+    qd = dev(q) if model == "bsm" else None
+    fl = dev(flag, torch.int8)
+    g = oracle.greeks(model, S, K, T, r, q, so, flag)
+    gd = fv.greeks(model, dev(S), dev(K), dev(T), dev(r), dev(so), flag=fl, q=qd)
+    # magnitudes of theta's terms (the value is -dP/dT)
+    from scipy.special import ndtr
+    pdf1 = np.exp(-0.5 * d1 * d1) / np.sqrt(2 * np.pi)
+    Dq = np.exp(-q * T)
+    if model == "black76":
+        theta_terms = np.abs(r * P) + D * Fx * pdf1 * so / (2 * np.sqrt(T))
+    else:
+        theta_terms = (S * Dq * pdf1 * so / (2 * np.sqrt(T)) + np.abs(r * K * D * ndtr(flag * d2)) +
+                       np.abs(q * S * Dq * ndtr(flag * d1)))
+    tiny = 1e-300
+    for name in ("delta", "gamma", "vega", "theta", "rho"):
+        a, b = host(gd[name]), g[name]
+        scale = theta_terms if name == "theta" else np.abs(b)
+        tol = 64 * U * kappa * scale + tiny
+        bad = ~(np.abs(a - b) <= tol)
+        print("fuzz-greeks/%s/%s: max err/tol=%.3g" % (model, name, np.max(np.abs(a - b) / tol)))
+        assert bad.sum() == 0, (model, name, np.where(bad)[0][:5], a[bad][:5], b[bad][:5],
+                                (np.abs(a - b) / tol)[bad][:5])
+    w = np.random.default_rng(7).standard_normal(len(S))
+    gr = fv.implied_vol_backward(model, dev(P), dev(S), dev(K), dev(T), dev(r), dev(so), dev(w),
+                                 flag=fl, q=qd)
+    go = oracle.iv_grad(model, P, S, K, T, r, q, flag) * w[:, None]
+    vega = np.abs(g["vega"])
+    names = ("price", "fs", "K", "T", "r", "q") if model == "bsm" else ("price", "fs", "K", "T", "r")
+    for j, name in enumerate(names):
+        a, b = host(gr[name]), go[:, j]
+        fin = np.isfinite(b) & (np.abs(b) < 1e300)
+        scale = np.abs(w) * theta_terms / vega if name == "T" else np.abs(b)
+        tol = 64 * U * kappa * scale + tiny
+        bad = fin & ~(np.abs(a - b) <= tol)
+        print("fuzz-grad/%s/%s: n=%d max err/tol=%.3g" % (model, name, fin.sum(),
+                                                         np.max((np.abs(a - b) / tol)[fin])))
+        assert bad.sum() == 0, (model, name, np.where(bad)[0][:5], a[bad][:5], b[bad][:5],
+                                (np.abs(a - b) / tol)[bad][:5])
