@@ -882,6 +882,8 @@ int parse_tuning(const char* path, std::string* text, std::string* arch,
       return bad("entry without kernel, model, bucket, block or qpt");
     if (k < 0 || k >= FV_KERNEL_COUNT || m < 0 || m >= kModels || b < 0 || b >= kBuckets)
       return bad("entry out of range");
+    // range-checked before the narrowing to int
+    if (blk < 1 || blk > 1 << 16 || qq < 1 || qq > 1 << 16) return bad("invalid launch shape");
     if (!valid_shape((int)blk, (int)qq) || queue_bytes((int)k, (int)blk, (int)qq) > kMaxQueueBytes)
       return bad("invalid launch shape");
     float ms = 0.0f;
@@ -1198,7 +1200,12 @@ int fv_autotune(int kernel, int model, int64_t n_hint, void* stream) {
       return fail(FV_E_HIP, "fv_autotune: device allocation failed");
     }
   hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+  if (hipEventCreate(&e0) != hipSuccess) {
+    release();
+    return fail(FV_E_HIP, "fv_autotune: event creation failed");
+  }
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
     release();
     return fail(FV_E_HIP, "fv_autotune: event creation failed");
   }

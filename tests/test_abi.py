@@ -120,6 +120,8 @@ def test_tuning_file_validation_and_shape_query(lib, tmp_path):
                  '[{"kernel": 1, "model": 2, "bucket": 3, "block": 96, "qpt": 1}]}',
         "field": '{"format": "fastvol-tuning", "version": 1, "arch": "x", "entries": '
                  '[{"kernel": 1, "model": 2, "block": 128, "qpt": 1}]}',
+        "wide": '{"format": "fastvol-tuning", "version": 1, "arch": "x", "entries": '
+                '[{"kernel": 1, "model": 2, "bucket": 3, "block": 4294967552, "qpt": 1}]}',
     }
     for name, text in bad.items():
         p = tmp_path / (name + ".json")
