@@ -119,34 +119,54 @@ def make_inputs(n, torch, fv):
     return wl, d(Ph), S, K, T, r, q, flag
 
 
-def cpu_baseline(wl, P, sample):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(wl, P, sample, reps=3):
+    """The oracle, untuned, on `sample` quotes strided over the workload: all
+    its OpenMP threads, then one thread on every 10th of those quotes; the
+    wall-clock median of `reps` runs of each."""
     import oracle
     idx = np.linspace(0, wl.n - 1, sample).astype(np.int64)
     sub = wl.take(idx)
     Ps = P[idx]
     oracle._load()
     threads = oracle.num_threads()
-    t0 = time.perf_counter()
-    oracle.implied_vol("bsm", Ps, sub.fs, sub.K, sub.T, sub.r, sub.q, sub.flag)
-    dt = time.perf_counter() - t0
-    # the same oracle on one thread, on every 10th quote of that sample
+
+    def wall(fn):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    dt = wall(lambda: oracle.implied_vol("bsm", Ps, sub.fs, sub.K, sub.T, sub.r, sub.q, sub.flag))
     s1 = slice(0, None, 10)
     oracle.set_threads(1)
     try:
-        t1 = time.perf_counter()
-        oracle.implied_vol("bsm", Ps[s1], sub.fs[s1], sub.K[s1], sub.T[s1], sub.r[s1], sub.q[s1],
-                           sub.flag[s1])
-        dt1 = time.perf_counter() - t1
+        dt1 = wall(lambda: oracle.implied_vol("bsm", Ps[s1], sub.fs[s1], sub.K[s1], sub.T[s1],
+                                              sub.r[s1], sub.q[s1], sub.flag[s1]))
     finally:
         oracle.set_threads(threads)
     n1 = len(Ps[s1])
     return {"value": sample / dt, "unit": "implied vols/s", "cores": threads,
             "kind": "oracle",
             "sample": "%d quotes evenly strided over the 10M-quote workload, binary128 exact "
-                      "root, OpenMP over %d threads, %.2f s wall" % (sample, threads, dt),
+                      "root, OpenMP over %d threads, median of %d runs %.2f s wall"
+                      % (sample, threads, reps, dt),
             "single_thread_value": n1 / dt1,
-            "single_thread_sample": "every 10th quote of that sample (%d), one thread, %.2f s wall"
-                                    % (n1, dt1)}
+            "single_thread_sample": "every 10th quote of that sample (%d), one thread, median of "
+                                    "%d runs %.2f s wall" % (n1, reps, dt1),
+            "host": {"cpu_model": _cpu_model(), "nproc": os.cpu_count()}}
 
 
 def _time(torch, fn, reps=10, warm=2):
