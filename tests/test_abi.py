@@ -142,3 +142,24 @@ def test_tuning_file_validation_and_shape_query(lib, tmp_path):
     # one quote: one-wave workgroups, one quote per thread
     assert lib.fv_launch_shape(1, 2, 1, ctypes.byref(b), ctypes.byref(q)) == N.FV_OK
     assert (b.value, q.value) == (64, 1)
+
+
+def test_missing_library_raises_instead_of_falling_back(tmp_path):
+    """With no built library the binding raises: there is no CPU path to
+    fall back to.  Run in a child process so this process keeps its loaded
+    library."""
+    import subprocess
+    import sys
+    code = ("import paper_2604_27210_amd as fv\n"
+            "from paper_2604_27210_amd import _native as N\n"
+            "try:\n"
+            "    N.load()\n"
+            "except N.FastvolError as e:\n"
+            "    print('raised:', e)\n"
+            "else:\n"
+            "    raise SystemExit('loaded a library that does not exist')\n")
+    env = dict(os.environ, FASTVOL_LIBRARY=str(tmp_path / "absent" / "libfastvol.so"))
+    res = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True,
+                         text=True, timeout=300)
+    assert res.returncode == 0, res.stderr[-2000:]
+    assert "raised: libfastvol.so is not built" in res.stdout
