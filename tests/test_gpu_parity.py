@@ -498,3 +498,47 @@ def test_fuzz_greeks_and_gradient(fv, model):
                                                          np.max((np.abs(a - b) / tol)[fin])))
         assert bad.sum() == 0, (model, name, np.where(bad)[0][:5], a[bad][:5], b[bad][:5],
                                 (np.abs(a - b) / tol)[bad][:5])
+
+
+def test_chains_edge_structures(fv):
+    """Ragged structures the configured chains never produce: chains with
+    no maturities (also leading and trailing), maturities with no quotes,
+    one quote, a wave and a wave plus one, and thousands; forwards over
+    seven decades, T from 1e-5 to 30 years, r from -0.1 to 0.3, |z| <= 8.
+    The chain kernel must equal the flat kernel bitwise (LBR) and both
+    solvers must match the oracle."""
+    rng = np.random.default_rng(41)
+    n_chains = 200
+    mpc = rng.choice([0, 1, 2, 5, 30], n_chains, p=[0.1, 0.3, 0.3, 0.2, 0.1])
+    mpc[:3] = 0
+    mpc[-3:] = 0
+    n_mat = int(mpc.sum())
+    qpm = rng.choice([0, 1, 3, 64, 65, 700, 5000], n_mat, p=[0.15, 0.2, 0.2, 0.15, 0.13, 0.15, 0.02])
+    cmo = np.concatenate([[0], np.cumsum(mpc)]).astype(np.int64)
+    mqo = np.concatenate([[0], np.cumsum(qpm)]).astype(np.int64)
+    n = int(mqo[-1])
+    F = np.exp(rng.uniform(np.log(1e-2), np.log(1e5), n_chains))
+    r = rng.uniform(-0.1, 0.3, n_chains)
+    T = np.exp(rng.uniform(np.log(1e-5), np.log(30.0), n_mat))
+    chain_of_mat = np.repeat(np.arange(n_chains), mpc)
+    mat_of_q = np.repeat(np.arange(n_mat), qpm)
+    Fq, rq, Tq = F[chain_of_mat][mat_of_q], r[chain_of_mat][mat_of_q], T[mat_of_q]
+    sig = np.exp(rng.uniform(np.log(1e-3), np.log(5.0), n))
+    z = rng.uniform(-8, 8, n)
+    K = Fq * np.exp(-z * sig * np.sqrt(Tq))
+    flag = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+    P = oracle.price("black76", Fq, K, Tq, rq, 0.0, sig, flag)
+    for solver in ("lbr", "halley"):
+        sc, stc = fv.implied_vol_chains(dev(cmo, torch.int64), dev(mqo, torch.int64), dev(F), dev(r),
+                                        dev(T), dev(P), dev(K), dev(flag, torch.int8), solver=solver)
+        sf, stf = fv.implied_vol("black76", dev(P), dev(Fq), dev(K), dev(Tq), dev(rq),
+                                 flag=dev(flag, torch.int8), solver=solver)
+        torch.cuda.synchronize()
+        if solver == "lbr":
+            assert torch.equal(stc, stf)
+            assert torch.equal(torch.nan_to_num(sc, nan=-1.0), torch.nan_to_num(sf, nan=-1.0))
+        res = compare_iv("black76", solver, P, Fq, K, Tq, rq, 0.0 * Tq, flag, host(sc), host(stc))
+        _report("chains-edge/%s (n=%d, %d maturities)" % (solver, n, n_mat), res)
+        assert len(res["status_bad"]) == 0, res["status_bad"][:5]
+        assert len(res["value_bad"]) == 0, (res["value_bad"][:5], res["max_ratio"])
+        assert len(res["nan_bad"]) == 0
