@@ -37,11 +37,11 @@ if ROOT not in sys.path:
 # The traffic figure is reported only while the kernel sources still hash to
 # ``source_sha256``; the FLOP figure is the algorithmic count of that source.
 LBR_PROFILE = {
-    "source_sha256": "a5bd5c22b4759b7f7f4d3acb086ce6e5c65d41698200fc2e40158b2bf742d74b",
+    "source_sha256": "1282d3f77e2e3332e6cbdfd617dc87147c3a1014c7a84ad165eca783583e3310",
     "flop_per_quote": 1165.9,
     "valu_per_quote": 1114.3,
-    "fetch_bytes_per_quote": 49.038,
-    "write_bytes_per_quote": 9.009,
+    "fetch_bytes_per_quote": 49.037,
+    "write_bytes_per_quote": 9.008,
 }
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 # VALU issue capacity at the nominal clock: 256 CUs x 4 SIMDs x 16 lanes,
