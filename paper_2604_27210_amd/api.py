@@ -133,6 +133,12 @@ class _Batch:
     def empty(self, dtype=torch.float64):
         return torch.empty(self.n, dtype=dtype, device=self.device)
 
+    def rows(self, names):
+        """One [len(names), n] float64 allocation, returned as a dict of its
+        rows (each contiguous)."""
+        block = torch.empty((len(names), self.n), dtype=torch.float64, device=self.device)
+        return {k: block[i] for i, k in enumerate(names)}
+
     def stream(self, stream=None) -> ctypes.c_void_p:
         return ctypes.c_void_p(_stream_ptr(stream, self.device))
 
@@ -231,7 +237,7 @@ def greeks(model, fs, K, T, r, sigma, flag="c", q=None, stream=None) -> dict:
     """delta, gamma, vega, theta (= -dP/dT), rho as raw per-unit derivatives."""
     b = _Batch(fs=fs, K=K, T=T, r=r, q=q, sigma=sigma, flag=flag)
     qs = b.quotes(None, fs, K, T, r, q, flag)
-    out = {k: b.empty() for k in ("delta", "gamma", "vega", "theta", "rho")}
+    out = b.rows(("delta", "gamma", "vega", "theta", "rho"))
     N.check(N.load().fv_greeks(_model(model), ctypes.byref(qs), b.arg(sigma, "sigma"),
                                *[_ptr(v) for v in out.values()],
                                b.stream(stream)), "fv_greeks")
@@ -245,7 +251,7 @@ def implied_vol_backward(model, price, fs, K, T, r, sigma, grad_sigma, flag="c",
     qs = b.quotes(price, fs, K, T, r, q, flag)
     _dev_tensor(sigma, "sigma")
     _dev_tensor(grad_sigma, "grad_sigma")
-    out = {k: b.empty() for k in ("price", "fs", "K", "T", "r", "q")}
+    out = b.rows(("price", "fs", "K", "T", "r", "q"))
     N.check(N.load().fv_implied_vol_backward(_model(model), ctypes.byref(qs), _ptr(sigma),
                                              _ptr(grad_sigma), *[_ptr(v) for v in out.values()],
                                              b.stream(stream)),
@@ -258,7 +264,7 @@ def price_backward(model, fs, K, T, r, sigma, grad_price, flag="c", q=None, stre
     b = _Batch(fs=fs, K=K, T=T, r=r, q=q, sigma=sigma, flag=flag, grad_price=grad_price)
     qs = b.quotes(None, fs, K, T, r, q, flag)
     _dev_tensor(grad_price, "grad_price")
-    out = {k: b.empty() for k in ("fs", "K", "T", "r", "q", "sigma")}
+    out = b.rows(("fs", "K", "T", "r", "q", "sigma"))
     N.check(N.load().fv_price_backward(_model(model), ctypes.byref(qs), b.arg(sigma, "sigma"),
                                        _ptr(grad_price), *[_ptr(v) for v in out.values()],
                                        b.stream(stream)), "fv_price_backward")
