@@ -395,7 +395,7 @@ def census(fv, torch, P, S, K, T, r, q, flag):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(quotes are independent, so a multi-GPU run would shard the batch by contiguous "
               "index ranges with no exchange)", file=sys.stderr)
         sys.exit(2)

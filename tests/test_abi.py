@@ -163,3 +163,14 @@ def test_missing_library_raises_instead_of_falling_back(tmp_path):
                          text=True, timeout=300)
     assert res.returncode == 0, res.stderr[-2000:]
     assert "raised: libfastvol.so is not built" in res.stdout
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU and says so for --gpus N > 1 (it exits
+    before touching any device)."""
+    import subprocess
+    import sys
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], cwd=ROOT,
+                         capture_output=True, text=True, timeout=300)
+    assert res.returncode != 0
+    assert "measures one GPU" in res.stdout + res.stderr
