@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_price(KQuotes q, fv_arg sigma, do
         fv::finite_d(qy) && fv::finite_d(sg) && fs > 0.0 && K > 0.0 && T > 0.0 &&
         sg >= 0.0 && (th == 1 || th == -1)) {
       const double F = fv::forward_of(MODEL, fs, T, r, qy);
-      const double D = fv::fexp(-r * T);
+      const double D = fv::fexp_prod(-r, T);
       p = fv::price_at(F, K, D, sg, fv::sqrt_pos(T), th);
     }
     out[i] = p;
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_greeks(KQuotes q, fv_arg sigma, G
         fv::finite_d(qy) && fv::finite_d(sg) && fs > 0.0 && K > 0.0 && T > 0.0 && sg > 0.0 &&
         (th == 1 || th == -1)) {
       const double F = fv::forward_of(MODEL, fs, T, r, qy);
-      const double D = fv::fexp(-r * T);
+      const double D = fv::fexp_prod(-r, T);
       const double P = fv::price_at(F, K, D, sg, fv::sqrt_pos(T), th);
       gr = fv::greeks_at(MODEL, fs, K, T, r, qy, sg, th, F, D, P);
     }
@@ -446,7 +446,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_price_backward(KQuotes q, fv_arg 
         fv::finite_d(qy) && fv::finite_d(sg) && fs > 0.0 && K > 0.0 && T > 0.0 && sg > 0.0 &&
         (th == 1 || th == -1)) {
       const double F = fv::forward_of(MODEL, fs, T, r, qy);
-      const double D = fv::fexp(-r * T);
+      const double D = fv::fexp_prod(-r, T);
       const double P = fv::price_at(F, K, D, sg, fv::sqrt_pos(T), th);
       const fv::PricePartials pp = fv::price_partials(MODEL, fs, K, T, r, qy, sg, th, F, D, P);
       v[0] = g * pp.dfs;

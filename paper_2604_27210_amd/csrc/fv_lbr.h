@@ -99,7 +99,7 @@ struct LbrResult {
 // eta3b = b'''/b'; step = nu (1 + eta2 nu/2) / (1 + nu (eta2 + eta3 nu/6)).
 template <bool LO>
 __host__ __device__ inline double householder3_step_t(int obj, double x, double s, double beta,
-                                                       double inv_ln_beta, double bmax_m_beta,
+                                                       double inv_ln_beta, double ln_bmax_m_beta,
                                                        const NBlack& nb) {
   const double is = rcp_lo(s);
   const double x2is2 = x * x * is * is;
@@ -111,16 +111,21 @@ __host__ __device__ inline double householder3_step_t(int obj, double x, double 
     e2 = eta;
     e3 = eta3b;
   } else {
-    // lower and upper share one log and one division.  The lower objective
-    // works in logarithms: ln b = ln b' + ln(b/b') and lambda = b'/b =
-    // 1/(b/b'), which stay accurate where b itself has left the normal range.
+    // lower and upper share one log and one division, and both work in
+    // logarithms through ratios to b', which stay in the normal range where
+    // b, b_max - b and b' themselves underflow deep in the wings:
+    //   lower  ln b          = ln b' + ln(b/b'),          lambda = 1/(b/b'),
+    //   upper  ln(b_max - b) = ln b' + ln((b_max - b)/b'), mu    = 1/((b_max - b)/b'),
+    // with (b_max - b)/b' from the complement form's E-free sum; in the
+    // difference form b_max - b is taken as it is.
     const bool lo = obj == kObjLower;
-    const double den = lo ? nb.ratio : nb.c;
-    const double iden = LO ? rcp_lo(den) : rcp(den);
-    const double w = lo ? iden : nb.bp * iden;  // lambda = b'/b  or  mu = b'/(b_max - b)
-    const double la = lo ? nb.ratio : bmax_m_beta * iden;
-    const double L = (LO ? flog_lo(la) : flog(la)) + (lo ? nb.lnbp : 0.0);
-    const double iw = lo ? nb.ratio : rcp_lo(w);
+    const bool comp = nb.form == kFormComplement;
+    const bool plain = !lo && !comp;
+    const double iw = lo ? nb.ratio : (comp ? nb.cratio : nb.c * rcp_lo_safe(nb.bp));
+    const double w = LO ? rcp_lo(iw) : rcp(iw);  // lambda or mu
+    const double la = plain ? nb.c : iw;
+    const double lnd = (LO ? flog_lo(la) : flog(la)) + (plain ? 0.0 : nb.lnbp);
+    const double L = lo ? lnd : ln_bmax_m_beta - lnd;
     if (lo) {
       const double iL = rcp_lo(L);
       nu = L * (1.0 - L * inv_ln_beta) * iw;
@@ -132,15 +137,17 @@ __host__ __device__ inline double householder3_step_t(int obj, double x, double 
       e3 = eta3b + 3.0 * w * eta + 2.0 * w * w;
     }
   }
-  double ds = fdiv_lo(nu * (1.0 + 0.5 * e2 * nu), 1.0 + nu * (e2 + e3 * nu * (1.0 / 6.0)));
-  if (!(ds == ds)) ds = 0.0;
+  // A step that is not a number (an evaluation beyond the binary64 range)
+  // becomes a halving (fmax ignores NaN); an infinite one leaves s infinite
+  // and the solve unconverged.
+  const double ds = fdiv_lo(nu * (1.0 + 0.5 * e2 * nu), 1.0 + nu * (e2 + e3 * nu * (1.0 / 6.0)));
   return fmax(ds, -0.5 * s);
 }
 
 __host__ __device__ inline double householder3_step(int obj, double x, double s, double beta,
-                                                     double inv_ln_beta, double bmax_m_beta,
+                                                     double inv_ln_beta, double ln_bmax_m_beta,
                                                      const NBlack& nb) {
-  return householder3_step_t<false>(obj, x, s, beta, inv_ln_beta, bmax_m_beta, nb);
+  return householder3_step_t<false>(obj, x, s, beta, inv_ln_beta, ln_bmax_m_beta, nb);
 }
 
 // Initial guess of the four-region scheme.  Boundary points: the inflection
@@ -276,7 +283,9 @@ __host__ __device__ __attribute__((always_inline)) inline LbrResult lbr_solve(
   int obj;
   double s = lbr_initial_guess(x, beta, bmax, ln_beta, &obj, trace);
   const double inv_ln_beta = rcp(ln_beta);
-  const double bmax_m_beta = bmax - beta;
+  // ln(b_max - beta), the upper objective's target, once per quote
+  double ln_bmax_m_beta = 0.0;
+  if (obj == kObjUpper) ln_bmax_m_beta = flog(bmax - beta);
   LbrResult res;
   // The first step starts ~1e-2 from the root and lands ~1e-8 from it, so it
   // runs at guess precision (b to ~1e-8); every later step is at full
@@ -286,7 +295,7 @@ __host__ __device__ __attribute__((always_inline)) inline LbrResult lbr_solve(
   if (max_steps > 0) {
     const NBlack nb = normalised_black_t<true>(x, s, bmax);
     if (trace) *trace |= (uint32_t)nb.form << 8;
-    ds = householder3_step_t<true>(obj, x, s, beta, inv_ln_beta, bmax_m_beta, nb);
+    ds = householder3_step_t<true>(obj, x, s, beta, inv_ln_beta, ln_bmax_m_beta, nb);
     s += ds;
     it = 1;
   }
@@ -294,7 +303,7 @@ __host__ __device__ __attribute__((always_inline)) inline LbrResult lbr_solve(
     if (it >= min_steps && !(fabs(ds) > step_tol * s)) break;
     const NBlack nb = normalised_black(x, s, bmax);
     if (trace) *trace |= (uint32_t)nb.form << (8 + 2 * it);
-    ds = householder3_step(obj, x, s, beta, inv_ln_beta, bmax_m_beta, nb);
+    ds = householder3_step(obj, x, s, beta, inv_ln_beta, ln_bmax_m_beta, nb);
     s += ds;
   }
   if (trace) *trace |= (uint32_t)(it - 2) << 2;

@@ -327,6 +327,8 @@ struct NBlack {
   double c;      // b_max - b(x, s)
   double bp;     // db/ds
   double ratio;  // b / b' (difference form; b/b' from b in the complement form)
+  double cratio; // (b_max - b) / b' in the complement form, free of the
+                 // common factor E (b_max - b and b' underflow together)
   double lnbp;   // ln b' = -(h^2 + t^2)/2 - ln sqrt(2 pi)
   int form;      // evaluation form taken (kFormDifference or kFormComplement)
 };
@@ -348,6 +350,7 @@ __host__ __device__ inline NBlack normalised_black_t(double x, double s, double 
     r.c = bmax - r.b;
     r.bp = atm ? kInvSqrt2Pi : 0.0;
     r.ratio = atm ? s : 0.0;
+    r.cratio = __builtin_inf();
     r.lnbp = atm ? -kLnSqrt2Pi : -__builtin_inf();
     r.form = kFormDifference;
     return r;
@@ -377,6 +380,7 @@ __host__ __device__ inline NBlack normalised_black_t(double x, double s, double 
   if (!comp) {
     constexpr double k2BZ = 2.0 * (kB - coef::kErfcxZ0);
     r.ratio = kSqrtPi * t * R1 * R2 * fma(-k2BZ * R1, D, B);
+    r.cratio = __builtin_inf();  // not used in this form
     r.b = r.bp * r.ratio;
     r.c = bmax - r.b;
     r.form = kFormDifference;
@@ -384,7 +388,9 @@ __host__ __device__ inline NBlack normalised_black_t(double x, double s, double 
     // p(y1) = p(y2) + (y1 - y2) D: y1 <= y2 and D <= 0, so both terms are
     // non-negative
     const double A = fma(y1 - y2, D, B);
-    r.c = 0.5 * E * fma(A, R1, B * R2);
+    const double S = fma(A, R1, B * R2);  // erfcx(-q1) + erfcx(q2)
+    r.c = 0.5 * E * S;
+    r.cratio = kSqrtPiOver2 * S;
     r.b = bmax - r.c;
     r.ratio = r.b * (LO ? rcp_lo(r.bp) : rcp(r.bp));
     r.form = kFormComplement;

@@ -52,11 +52,35 @@ __host__ __device__ inline double sqrt_pos(double T) {
   return Ts * rsqrt(Ts) * (tiny ? 0x1p-100 : 1.0);
 }
 
+// e^{a b} with the rounding error of the exponent carried into the result:
+// a b = p + e exactly (p = fl(a b), e = fma(a, b, -p)) and e^{p + e} =
+// e^p (1 + e) to first order (|e| <= 2^-53 |p|).  Over long maturities r T
+// reaches tens, where dropping e would put tens of ulps into the forward or
+// the discount factor, errors that the inputs' own conditioning does not
+// cover (the exact sensitivity to r cancels between forward and discount).
+__host__ __device__ inline double fexp_prod(double a, double b) {
+  const double p = a * b;
+  const double e = fma(a, b, -p);
+  const double E = fexp(p);
+  return fma(E, e, E);
+}
+
+// e^{(r - q) T}, carrying the rounding of r - q as well (Knuth's two-sum:
+// r - q = c + ce exactly)
+__host__ __device__ inline double fexp_carry(double r, double q, double T) {
+  const double c = r - q;
+  const double bb = c - r;
+  const double ce = (r - (c - bb)) + (-q - bb);
+  const double p = c * T;
+  const double e = fma(c, T, -p) + ce * T;
+  const double E = fexp(p);
+  return fma(E, e, E);
+}
+
 __host__ __device__ inline double forward_of(int model, double fs, double T, double r,
                                              double q) {
   if (model == kBlack76) return fs;
-  const double carry = (model == kBlackScholesMerton) ? (r - q) : r;
-  return fs * fexp(carry * T);
+  return fs * (model == kBlackScholesMerton ? fexp_carry(r, q, T) : fexp_prod(r, T));
 }
 
 __host__ __device__ inline Reduced reduce_quote(int model, double price, double fs, double K,
@@ -71,8 +95,8 @@ __host__ __device__ inline Reduced reduce_quote(int model, double price, double 
   if (!ok_in) { o.status = kQInvalid; return o; }
   const double F = forward_of(model, fs, T, r, q);
   if (!(F >= kDblMin && finite_d(F))) { o.status = kQInvalid; return o; }
-  const double D = fexp(-r * T);
-  const double Pu = price * fexp(r * T);
+  const double D = fexp_prod(-r, T);
+  const double Pu = price * fexp_prod(r, T);
   const double I = theta > 0 ? fmax(F - K, 0.0) : fmax(K - F, 0.0);
   const double M = theta > 0 ? F : K;
   o.F = F;
@@ -200,7 +224,7 @@ __host__ __device__ inline IvGrad iv_gradient(int model, double fs, double K, do
                                               double price) {
   IvGrad o;
   const double F = forward_of(model, fs, T, r, q);
-  const double D = fexp(-r * T);
+  const double D = fexp_prod(-r, T);
   const PricePartials pp = price_partials(model, fs, K, T, r, q, sigma, theta, F, D, price);
   const double iv = 1.0 / pp.dsigma;
   o.dP = iv;

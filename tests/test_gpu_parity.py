@@ -542,3 +542,46 @@ def test_chains_edge_structures(fv):
         assert len(res["status_bad"]) == 0, res["status_bad"][:5]
         assert len(res["value_bad"]) == 0, (res["value_bad"][:5], res["max_ratio"])
         assert len(res["nan_bad"]) == 0
+
+
+@pytest.mark.parametrize("model", ["black76", "bs", "bsm"])
+def test_fuzz_long_dated_and_far_wings(fv, model):
+    """Beyond the first fuzz: S over ten decades, T up to 80 years with r up
+    to 0.5 (exponents r T of tens, where the forward and discount factor
+    must carry the rounding of their exponents), negative q, sigma up to 20
+    and |z| up to 15, plus quotes deep in the upper wing (|x| in [400, 650],
+    s in [28, 50]), where iterates above the root meet b' and b_max - b
+    below the normal range together.
+    Both solvers against the oracle."""
+    rng = np.random.default_rng({"black76": 51, "bs": 52, "bsm": 53}[model])
+    n, m = 100_000, 4_000
+    S = np.exp(rng.uniform(np.log(1e-4), np.log(1e6), n + m))
+    T = np.exp(rng.uniform(np.log(1e-7), np.log(80.0), n + m))
+    r = rng.uniform(-0.2, 0.5, n + m)
+    q = rng.uniform(-0.1, 0.4, n + m) if model == "bsm" else np.zeros(n + m)
+    sig = np.exp(rng.uniform(np.log(1e-5), np.log(20.0), n + m))
+    z = rng.uniform(-15, 15, n + m)
+    flag = np.where(rng.random(n + m) < 0.5, 1, -1).astype(np.int8)
+    with np.errstate(over="ignore", invalid="ignore"):  # overflowing strikes are invalid quotes
+        F, D = forward_discount(model, S, T, r, q)
+        K = F * np.exp(-z * sig * np.sqrt(T))
+    # the far upper wing: out-of-the-money |x| and total volatility s chosen
+    # (calls K = F e^{|x|}, puts K = F e^{-|x|}; forwards kept so that K
+    # stays finite)
+    xw = rng.uniform(400.0, 650.0, m)
+    sw = rng.uniform(28.0, 50.0, m)
+    S[n:] = np.exp(rng.uniform(np.log(1e-2), np.log(1e2), m))
+    T[n:] = rng.uniform(0.5, 20.0, m)
+    sig[n:] = sw / np.sqrt(T[n:])
+    F, D = forward_discount(model, S, T, r, q)
+    K[n:] = F[n:] * np.exp(flag[n:] * xw)
+    P = oracle.price(model, S, K, T, r, q, sig, flag)
+    for solver in ("lbr", "halley"):
+        s, st = fv.implied_vol(model, dev(P), dev(S), dev(K), dev(T), dev(r),
+                               flag=dev(flag, torch.int8), q=dev(q) if model == "bsm" else None,
+                               solver=solver)
+        res = compare_iv(model, solver, P, S, K, T, r, q, flag, host(s), host(st))
+        _report("fuzz-far/%s/%s" % (model, solver), res)
+        assert len(res["status_bad"]) == 0, res["status_bad"][:5]
+        assert len(res["value_bad"]) == 0, (res["value_bad"][:5], res["max_ratio"])
+        assert len(res["nan_bad"]) == 0
