@@ -74,14 +74,25 @@ def boundary_ambiguous(model, P, fs, K, T, r, q, flag, ulps=16, u=None):
     arithmetic deciding the status (binary64 by default; 2^-24 for the
     binary32 solver)."""
     u = U if u is None else u
-    F, D = forward_discount(model, fs, T, r, q)
-    Pu = P / D
+    # the distances are measured in x87 extended precision (64-bit
+    # significand): a binary64 forward e^{(r-q)T} or discount e^{-rT} carries
+    # the rounding of its exponent, tens of ulps at long maturities, which
+    # would shift the window by more than its width
+    L = np.longdouble
+    fs_, K_, T_, r_, q_ = (np.asarray(v, dtype=L) for v in (fs, K, T, r, q))
+    if model == "black76":
+        F = fs_
+    elif model == "bs":
+        F = fs_ * np.exp(r_ * T_)
+    else:
+        F = fs_ * np.exp((r_ - q_) * T_)
+    Pu = np.asarray(P, dtype=L) * np.exp(r_ * T_)
     call = np.asarray(flag) > 0
-    intrinsic = np.where(call, np.maximum(F - K, 0.0), np.maximum(K - F, 0.0))
-    upper = np.where(call, F, K)
-    scale = np.maximum(np.abs(Pu), np.maximum(np.abs(F), np.abs(K)))
+    intrinsic = np.where(call, np.maximum(F - K_, 0.0), np.maximum(K_ - F, 0.0))
+    upper = np.where(call, F, K_)
+    scale = np.maximum(np.abs(Pu), np.maximum(np.abs(F), np.abs(K_)))
     near = (np.abs(Pu - intrinsic) <= ulps * u * scale) | (np.abs(upper - Pu) <= ulps * u * scale)
-    return near
+    return np.asarray(near, dtype=bool)
 
 
 def compare_iv(model, solver, P, fs, K, T, r, q, flag, sig, st):
