@@ -28,6 +28,7 @@
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC fv_oracle.c
  *        -lquadmath -lm
  */
+#include <float.h>
 #include <math.h>
 #include <quadmath.h>
 #include <stdint.h>
@@ -186,13 +187,21 @@ static int d_status(int model, double price, double fs, double K, double T, doub
         return ORC_INVALID;
     if (fs <= 0 || K <= 0 || T <= 0 || (theta != 1 && theta != -1))
         return ORC_INVALID;
+    /* the library's input domain: S/F, K and the forward are normal binary64
+       numbers (subnormal ones are invalid inputs, not prices) */
+    if (fs < DBL_MIN || K < DBL_MIN)
+        return ORC_INVALID;
+    /* the forward and the undiscounted price correctly rounded to binary64
+       (exponents formed in binary128): a binary64 exponent r T would carry
+       its own rounding, tens of ulps of F at long maturities */
     double F;
     if (model == ORC_B76)
         F = fs;
     else
-        F = fs * exp(((model == ORC_BSM) ? (r - q) : r) * T);
-    double D = exp(-r * T);
-    double Pu = price / D;
+        F = (double)((qr)fs * expq((((model == ORC_BSM) ? ((qr)r - (qr)q) : (qr)r)) * (qr)T));
+    if (!(F >= DBL_MIN) || !isfinite(F))
+        return ORC_INVALID;
+    double Pu = (double)((qr)price * expq((qr)r * (qr)T));
     double I = theta > 0 ? (F > K ? F - K : 0.0) : (K > F ? K - F : 0.0);
     double M = theta > 0 ? F : K;
     if (Pu < I) return ORC_BELOW_INTRINSIC;
