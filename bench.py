@@ -37,11 +37,11 @@ if ROOT not in sys.path:
 # The traffic figure is reported only while the kernel sources still hash to
 # ``source_sha256``; the FLOP figure is the algorithmic count of that source.
 LBR_PROFILE = {
-    "source_sha256": "1282d3f77e2e3332e6cbdfd617dc87147c3a1014c7a84ad165eca783583e3310",
-    "flop_per_quote": 1165.9,
-    "valu_per_quote": 1114.3,
-    "fetch_bytes_per_quote": 49.037,
-    "write_bytes_per_quote": 9.008,
+    "source_sha256": "57c8fed4e959c2eb03cb9f050761acfaa007d76f5ab18a31433f3bc5bfd2a31b",
+    "flop_per_quote": 1179.9,
+    "valu_per_quote": 1134.7,
+    "fetch_bytes_per_quote": 49.036,
+    "write_bytes_per_quote": 9.009,
 }
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 # VALU issue capacity at the nominal clock: 256 CUs x 4 SIMDs x 16 lanes,
