@@ -87,12 +87,13 @@ def _prepare(fields: dict, flag):
         else:
             a = v.detach().to("cpu", torch.float64).numpy() if isinstance(v, torch.Tensor) \
                 else np.asarray(v, dtype=np.float64)
-            a = np.ascontiguousarray(np.broadcast_to(a, shape).reshape(-1))
+            # a writable copy: broadcast views are read-only
+            a = np.array(np.broadcast_to(a, shape).reshape(-1), dtype=np.float64)
             out[name] = torch.from_numpy(a).to("cuda")
     if isinstance(fl, int):
         fl_out = fl
     else:
-        f = np.ascontiguousarray(np.broadcast_to(fl, shape).reshape(-1))
+        f = np.array(np.broadcast_to(fl, shape).reshape(-1))
         fl_out = torch.from_numpy(f).to("cuda")
     # the library needs one per-quote array to size the batch
     if not any(isinstance(v, torch.Tensor) for v in out.values()) and \

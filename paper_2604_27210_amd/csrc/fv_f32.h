@@ -142,6 +142,25 @@ struct Reduced {
   uint8_t status;
 };
 
+// e^{a b} and e^{(r - q) T} with the rounding of the exponent carried into
+// the result, as in the binary64 path: a b = p + e exactly, e^{p + e} =
+// e^p (1 + e) to first order (and r - q = c + ce exactly by two-sum).
+__host__ __device__ inline float fexp_prod(float a, float b) {
+  const float p = a * b;
+  const float e = fmaf(a, b, -p);
+  const float E = fexp(p);
+  return fmaf(E, e, E);
+}
+__host__ __device__ inline float fexp_carry(float r, float q, float T) {
+  const float c = r - q;
+  const float bb = c - r;
+  const float ce = (r - (c - bb)) + (-q - bb);
+  const float p = c * T;
+  const float e = fmaf(c, T, -p) + ce * T;
+  const float E = fexp(p);
+  return fmaf(E, e, E);
+}
+
 __host__ __device__ inline Reduced reduce_quote(int model, float price, float fs, float K,
                                                 float T, float r, float q, int theta) {
   Reduced o;
@@ -150,10 +169,9 @@ __host__ __device__ inline Reduced reduce_quote(int model, float price, float fs
                      finite(q) && fs >= kFltMin && K >= kFltMin && T > 0.0f &&
                      (theta == 1 || theta == -1);
   if (!ok_in) { o.status = 4; return o; }
-  const float carry = model == 0 ? 0.0f : (model == 2 ? r - q : r);
-  const float F = model == 0 ? fs : fs * fexp(carry * T);
+  const float F = model == 0 ? fs : fs * (model == 2 ? fexp_carry(r, q, T) : fexp_prod(r, T));
   if (!(F >= kFltMin && finite(F))) { o.status = 4; return o; }
-  const float Pu = price * fexp(r * T);
+  const float Pu = price * fexp_prod(r, T);
   const float I = theta > 0 ? fmaxf(F - K, 0.0f) : fmaxf(K - F, 0.0f);
   const float M = theta > 0 ? F : K;
   o.sqrtT = sqrtf(T);

@@ -91,7 +91,8 @@ def boundary_ambiguous(model, P, fs, K, T, r, q, flag, ulps=16, u=None):
     intrinsic = np.where(call, np.maximum(F - K_, 0.0), np.maximum(K_ - F, 0.0))
     upper = np.where(call, F, K_)
     scale = np.maximum(np.abs(Pu), np.maximum(np.abs(F), np.abs(K_)))
-    near = (np.abs(Pu - intrinsic) <= ulps * u * scale) | (np.abs(upper - Pu) <= ulps * u * scale)
+    with np.errstate(invalid="ignore", over="ignore"):  # infinite inputs are not near anything
+        near = (np.abs(Pu - intrinsic) <= ulps * u * scale) | (np.abs(upper - Pu) <= ulps * u * scale)
     return np.asarray(near, dtype=bool)
 
 
