@@ -37,10 +37,10 @@ if ROOT not in sys.path:
 # The traffic figure is reported only while the kernel sources still hash to
 # ``source_sha256``; the FLOP figure is the algorithmic count of that source.
 LBR_PROFILE = {
-    "source_sha256": "57c8fed4e959c2eb03cb9f050761acfaa007d76f5ab18a31433f3bc5bfd2a31b",
+    "source_sha256": "be5f02178d1deaf8a33dd50d2bfd2ee895f8e172f48b4c1e68905da1033132d8",
     "flop_per_quote": 1179.9,
     "valu_per_quote": 1134.7,
-    "fetch_bytes_per_quote": 49.036,
+    "fetch_bytes_per_quote": 49.035,
     "write_bytes_per_quote": 9.009,
 }
 FP64_VECTOR_PEAK_TFLOPS = 78.6

@@ -1182,7 +1182,7 @@ int fv_autotune(int kernel, int model, int64_t n_hint, void* stream) {
     return p;
   };
   auto release = [&]() {
-    for (void* p : bufs) hipFree(p);
+    for (void* p : bufs) (void)hipFree(p);
     bufs.clear();
   };
   double *S = (double*)alloc(n * 8), *K = (double*)alloc(n * 8), *T = (double*)alloc(n * 8),
@@ -1205,7 +1205,7 @@ int fv_autotune(int kernel, int model, int64_t n_hint, void* stream) {
     return fail(FV_E_HIP, "fv_autotune: event creation failed");
   }
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     release();
     return fail(FV_E_HIP, "fv_autotune: event creation failed");
   }
@@ -1295,18 +1295,20 @@ int fv_autotune(int kernel, int model, int64_t n_hint, void* stream) {
       g_tuning_kernel = kernel;
       g_tuning_shape = LaunchShape{b, qq};
       rc = run();  // warm-up
-      float tot = 0.0f, mn = 1e30f;
+      float mn = 1e30f;
       for (int rep = 0; rep < 3 && rc == FV_OK; ++rep) {
-        hipEventRecord(e0, s);
+        if (hipEventRecord(e0, s) != hipSuccess) {
+          rc = fail(FV_E_HIP, "fv_autotune: event record");
+          break;
+        }
         rc = run();
-        hipEventRecord(e1, s);
-        if (hipEventSynchronize(e1) != hipSuccess) rc = fail(FV_E_HIP, "fv_autotune: sync");
         float ms = 0.0f;
-        hipEventElapsedTime(&ms, e0, e1);
-        tot += ms;
+        if (rc == FV_OK && (hipEventRecord(e1, s) != hipSuccess ||
+                            hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          rc = fail(FV_E_HIP, "fv_autotune: event timing");
         mn = std::min(mn, ms);
       }
-      (void)tot;
       if (rc == FV_OK && mn < best_ms) {
         best_ms = mn;
         best = {b, qq};
@@ -1316,9 +1318,10 @@ int fv_autotune(int kernel, int model, int64_t n_hint, void* stream) {
   g_tuning_kernel = -1;
   if (rc == FV_OK && best.block)
     g_tuned[kernel][tuned_model][bucket] = Tuned{best.block, best.qpt, best_ms};
-  hipStreamSynchronize(s);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  // best-effort cleanup: an error here cannot change the result above
+  (void)hipStreamSynchronize(s);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   release();
   return rc;
 }

@@ -437,8 +437,24 @@ def test_fuzz_extreme_ranges(fv, model):
         assert len(res["nan_bad"]) == 0
 
 
+def _long_dated_quotes(model, n=40_000):
+    """Long maturities with high rates (r T up to 40), negative q."""
+    rng = np.random.default_rng({"black76": 61, "bs": 62, "bsm": 63}[model])
+    S = np.exp(rng.uniform(np.log(1e-2), np.log(1e4), n))
+    T = rng.uniform(20.0, 80.0, n)
+    r = rng.uniform(-0.2, 0.5, n)
+    q = rng.uniform(-0.1, 0.4, n) if model == "bsm" else np.zeros(n)
+    sig = np.exp(rng.uniform(np.log(1e-2), np.log(1.0), n))
+    z = rng.uniform(-6, 6, n)
+    F, D = forward_discount(model, S, T, r, q)
+    K = F * np.exp(-z * sig * np.sqrt(T))
+    flag = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+    return rng, S, K, T, r, q, sig, flag
+
+
+@pytest.mark.parametrize("recipe", ["wide", "long_dated"])
 @pytest.mark.parametrize("model", ["black76", "bs", "bsm"])
-def test_fuzz_greeks_and_gradient(fv, model):
+def test_fuzz_greeks_and_gradient(fv, model, recipe):
     """Greeks and the implied-volatility gradient at the fuzz quotes' exact
     roots (the oracle's, rounded to binary64), against the oracle's binary128
     values.  The bound follows the conditioning of the binary64 arguments:
@@ -447,7 +463,7 @@ def test_fuzz_greeks_and_gradient(fv, model):
     into a relative error of (|d| + 1) times that; theta and dP/dT are sums
     of terms of both signs, so their bound scales with the sum of the
     terms' magnitudes instead of the value."""
-    _, S, K, T, r, q, sig, flag = _fuzz_quotes(model)
+    _, S, K, T, r, q, sig, flag = (_fuzz_quotes if recipe == "wide" else _long_dated_quotes)(model)
     P = oracle.price(model, S, K, T, r, q, sig, flag)
     so, sto = oracle.implied_vol(model, P, S, K, T, r, q, flag)
     ok = (sto == 0) & (so > 0)
@@ -479,7 +495,8 @@ def test_fuzz_greeks_and_gradient(fv, model):
         scale = theta_terms if name == "theta" else np.abs(b)
         tol = 64 * U * kappa * scale + tiny
         bad = ~(np.abs(a - b) <= tol)
-        print("fuzz-greeks/%s/%s: max err/tol=%.3g" % (model, name, np.max(np.abs(a - b) / tol)))
+        print("fuzz-greeks/%s/%s/%s: max err/tol=%.3g" % (recipe, model, name,
+                                                         np.max(np.abs(a - b) / tol)))
         assert bad.sum() == 0, (model, name, np.where(bad)[0][:5], a[bad][:5], b[bad][:5],
                                 (np.abs(a - b) / tol)[bad][:5])
     w = np.random.default_rng(7).standard_normal(len(S))
@@ -494,8 +511,8 @@ def test_fuzz_greeks_and_gradient(fv, model):
         scale = np.abs(w) * theta_terms / vega if name == "T" else np.abs(b)
         tol = 64 * U * kappa * scale + tiny
         bad = fin & ~(np.abs(a - b) <= tol)
-        print("fuzz-grad/%s/%s: n=%d max err/tol=%.3g" % (model, name, fin.sum(),
-                                                         np.max((np.abs(a - b) / tol)[fin])))
+        print("fuzz-grad/%s/%s/%s: n=%d max err/tol=%.3g" % (recipe, model, name, fin.sum(),
+                                                            np.max((np.abs(a - b) / tol)[fin])))
         assert bad.sum() == 0, (model, name, np.where(bad)[0][:5], a[bad][:5], b[bad][:5],
                                 (np.abs(a - b) / tol)[bad][:5])
 
