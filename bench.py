@@ -37,10 +37,10 @@ if ROOT not in sys.path:
 # The traffic figure is reported only while the kernel sources still hash to
 # ``source_sha256``; the FLOP figure is the algorithmic count of that source.
 LBR_PROFILE = {
-    "source_sha256": "be5f02178d1deaf8a33dd50d2bfd2ee895f8e172f48b4c1e68905da1033132d8",
+    "source_sha256": "465ea158f41d1fdeeb8138b4c0da029c34d929f81703d1d3799ba0be7e78cab9",
     "flop_per_quote": 1179.9,
-    "valu_per_quote": 1134.7,
-    "fetch_bytes_per_quote": 49.035,
+    "valu_per_quote": 1128.0,
+    "fetch_bytes_per_quote": 49.039,
     "write_bytes_per_quote": 9.009,
 }
 FP64_VECTOR_PEAK_TFLOPS = 78.6

@@ -179,7 +179,14 @@ __host__ __device__ inline Reduced reduce_quote(int model, float price, float fs
   if (Pu == I) { o.status = 1; return o; }
   if (Pu >= M) { o.status = 3; return o; }
   const int th = (I > 0.0f) ? -theta : theta;
-  const float lx = flog(F * rcp(K));
+  // ln(F/K) from the ratio, or from the two logarithms where F/K leaves the
+  // binary32 normal range (|ln(F/K)| beyond about 87)
+  const float fk = F * rcp(K);
+  float lx;
+  if (fk > kFltMin && fk < 0x1p127f)
+    lx = flog(fk);
+  else
+    lx = flog(F) - flog(K);
   o.x = th > 0 ? lx : -lx;
   const float isq = rsqrt(F) * rsqrt(K);  // F K leaves binary32 beyond about 1e+-19
   o.beta = (Pu - I) * isq;
@@ -242,8 +249,10 @@ __host__ __device__ __attribute__((always_inline)) inline HalleyState halley_sol
 // sqrt(lo) sqrt(hi)).
 __host__ __device__ inline float bisection_solve(float x, float beta, float bmax, float lo,
                                                  float hi, float rel_tol) {
-  if (!(lo > 0.0f)) lo = 1e-8f;
-  if (!(hi < 3.0e38f)) hi = 50.0f;
+  // an end the caller's bracket did not fix: far below any root, and far
+  // above it (b_max - b(s) is below b_max 2^-24 once s exceeds ~12 + |x|/10)
+  if (!(lo > 0.0f)) lo = 1e-30f;
+  if (!(hi < 3.0e38f)) hi = 1e3f;
   for (int k = 0; k < 100 && hi - lo > rel_tol * hi; ++k) {
     const float mid = sqrtf(lo) * sqrtf(hi);
     const NBlack nb = normalised_black(x, mid, bmax);

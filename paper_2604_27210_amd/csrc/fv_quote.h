@@ -106,7 +106,14 @@ __host__ __device__ inline Reduced reduce_quote(int model, double price, double 
   if (Pu == I) { o.status = kQAtIntrinsic; return o; }
   if (Pu >= M) { o.status = kQAboveMax; return o; }
   const int th = (I > 0.0) ? -theta : theta;  // in the money: parity to OTM
-  const double lx = flog(F * rcp(K));
+  // ln(F/K) from the ratio, or from the two logarithms where F/K leaves the
+  // normal range (|ln(F/K)| beyond about 708)
+  const double fk = F * rcp(K);
+  double lx;
+  if (fk > kDblMin && fk < 0x1p1023)
+    lx = flog(fk);
+  else
+    lx = flog(F) - flog(K);
   o.x = th > 0 ? lx : -lx;
   // 1/sqrt(F K) as two factors: F K itself leaves the binary64 range once F
   // and K are beyond about 1e+-154, while the normalised quantities do not

@@ -117,3 +117,32 @@ def test_empty_and_invalid(fv):
     with pytest.raises(TypeError):
         fv.implied_vol_f32("bs", torch.ones(4, dtype=torch.float64, device="cuda"), 100.0, 100.0,
                            1.0, 0.0)
+
+
+@pytest.mark.parametrize("model", ["black76", "bs", "bsm"])
+def test_fuzz_extreme_ranges_f32(fv, model):
+    """Seeded binary32 quotes beyond the configured workloads: S over six
+    decades, T from 1e-6 to 80 years, r up to 0.5, sigma from 1e-3 to 20,
+    |z| up to 12 (strikes far enough out that F/K leaves the binary32
+    range), against the oracle under the contract above."""
+    rng = np.random.default_rng({"black76": 71, "bs": 72, "bsm": 73}[model])
+    n = 100_000
+    f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    S = f32(np.exp(rng.uniform(np.log(1e-2), np.log(1e4), n)))
+    T = f32(np.exp(rng.uniform(np.log(1e-6), np.log(80.0), n)))
+    r = f32(rng.uniform(-0.1, 0.5, n))
+    q = f32(rng.uniform(0.0, 0.3, n) if model == "bsm" else np.zeros(n))
+    sig = np.exp(rng.uniform(np.log(1e-3), np.log(20.0), n))
+    z = rng.uniform(-12, 12, n)
+    flag = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+    with np.errstate(all="ignore"):
+        F, D = forward_discount(model, S, T, r, q)
+        K = f32(F * np.exp(-z * sig * np.sqrt(T)))
+    keep = np.isfinite(K) & (K >= np.finfo(np.float32).tiny) & (K < 1e37)
+    S, K, T, r, q, sig, flag = (a[keep] for a in (S, K, T, r, q, sig, flag))
+    P = f32(oracle.price(model, S, K, T, r, q, sig, flag))
+    keep = np.isfinite(P) & ((P == 0) | (P >= np.finfo(np.float32).tiny))
+    S, K, T, r, q, flag, P = (a[keep] for a in (S, K, T, r, q, flag, P))
+    n_ok, worst = check(fv, model, P, S, K, T, r, q, flag)
+    print("f32 fuzz %s: solved %d of %d, max err/tol %.3g" % (model, n_ok, len(P), worst))
+    assert n_ok > 0.5 * len(P)
