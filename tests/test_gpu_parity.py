@@ -602,3 +602,29 @@ def test_fuzz_long_dated_and_far_wings(fv, model):
         assert len(res["status_bad"]) == 0, res["status_bad"][:5]
         assert len(res["value_bad"]) == 0, (res["value_bad"][:5], res["max_ratio"])
         assert len(res["nan_bad"]) == 0
+
+
+@pytest.mark.parametrize("model", ["black76", "bs", "bsm"])
+def test_price_fuzz_extreme_ranges(fv, model):
+    """fv_price over the fuzz quotes (sigma 1e-4..10, T 1e-6..50, |z| <= 12)
+    against the oracle's binary128 price, within 16 u of the price plus its
+    first-order sensitivity to rounding every input."""
+    _, S, K, T, r, q, sig, flag = _fuzz_quotes(model)
+    qd = dev(q) if model == "bsm" else None
+    p = host(fv.price(model, dev(S), dev(K), dev(T), dev(r), dev(sig), flag=dev(flag, torch.int8),
+                      q=qd))
+    po = oracle.price(model, S, K, T, r, q, sig, flag)
+    g = oracle.greeks(model, S, K, T, r, q, sig, flag)
+    F, D = forward_discount(model, S, T, r, q)
+    from scipy.special import ndtr
+    with np.errstate(all="ignore"):
+        d2 = np.log(F / K) / (sig * np.sqrt(T)) - 0.5 * sig * np.sqrt(T)
+        dPdK = -flag * D * ndtr(flag * d2)
+        # carry terms: r and q move the forward (and r the discount)
+        cond = (np.abs(g["delta"] * S) + np.abs(dPdK * K) + np.abs(g["theta"] * T) +
+                np.abs(g["vega"] * sig) + np.abs(g["rho"] * r) + np.abs(T * q * D * F) +
+                np.abs(r * T) * np.abs(po) + np.abs(r * T) * D * (F + K))
+    tol = 16 * U * (np.abs(po) + cond)
+    bad = ~(np.abs(p - po) <= tol)
+    print("price-fuzz/%s: max err/tol %.3g" % (model, np.nanmax(np.abs(p - po) / tol)))
+    assert bad.sum() == 0, (np.where(bad)[0][:5], p[bad][:5], po[bad][:5])
