@@ -75,7 +75,9 @@ enum fv_quote_status {
                                   for the implied-volatility entry points also
                                   S/F, K or the forward below the smallest
                                   normal number (or the forward overflowing) */
-    FV_Q_NOT_CONVERGED = 5     /* solver did not meet its tolerance (sigma kept) */
+    FV_Q_NOT_CONVERGED = 5     /* solver did not meet its tolerance, or its root was
+                                  not finite and positive (sigma keeps the last
+                                  iterate; NaN on the binary32 path) */
 };
 
 typedef struct {
