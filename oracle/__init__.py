@@ -148,6 +148,31 @@ def iv_grad(model, price_, fs, K, T, r, q, flag):
     return g
 
 
+def iv_rel_sens(model, price_, fs, K, T, r, q, flag):
+    """Signed relative sensitivities X d sigma/d X over X in (price, S-or-F,
+    K, T, r, q) at the exact root, shape (n, 6), formed in binary128 (finite
+    also where vega is far below the binary64 range)."""
+    n = _n(price_, fs, K, T, r, q, flag)
+    price_, fs, K, T, r, q = _bcast(n, price_, fs, K, T, r, q)
+    fl = _flags(flag, n)
+    e = np.empty((n, 6))
+    _load().orc_iv_rel_sens_n(ctypes.c_int(_model(model)), ctypes.c_int64(n), _p(price_),
+                              _p(fs), _p(K), _p(T), _p(r), _p(q), _p(fl), _p(e))
+    return e
+
+
+def iv_grad_at(model, fs, K, T, r, q, sigma, flag):
+    """The implicit-function gradient d sigma/d (price, S-or-F, K, T, r, q)
+    evaluated at the given sigma (not at the root), shape (n, 6)."""
+    n = _n(fs, K, T, r, q, sigma, flag)
+    fs, K, T, r, q, sigma = _bcast(n, fs, K, T, r, q, sigma)
+    fl = _flags(flag, n)
+    g = np.empty((n, 6))
+    _load().orc_iv_grad_at_n(ctypes.c_int(_model(model)), ctypes.c_int64(n), _p(fs), _p(K),
+                             _p(T), _p(r), _p(q), _p(sigma), _p(fl), _p(g))
+    return g
+
+
 def normalised_black(x, s, flag=1, with_residual=False):
     n = _n(x, s, flag)
     x, s = _bcast(n, x, s)

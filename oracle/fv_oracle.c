@@ -407,6 +407,69 @@ void orc_iv_grad_n(int model, int64_t n, const double *price, const double *fs,
     }
 }
 
+/* Signed relative sensitivities of the implied volatility,
+ *   e_X = X d sigma/d X   for X in (price, S or F, K, T, r, q),
+ * by the implicit-function theorem at the oracle's own root (the gradient
+ * above times the input), with the product formed in binary128 before the
+ * rounding to binary64.  For prices below the normal binary64 range, vega is
+ * far below it as well and 1/vega overflows binary64, while the product
+ * X/vega stays of the order of sigma; only this form keeps it finite.
+ * rel is row-major [n][6]; quotes without a root get NaN rows.  (r and q
+ * enter as absolute values: e_r = r d sigma/d r.) */
+void orc_iv_rel_sens_n(int model, int64_t n, const double *price, const double *fs,
+                       const double *K, const double *T, const double *r, const double *q,
+                       const int8_t *flag, double *rel)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        double *e = rel + 6 * i;
+        for (int j = 0; j < 6; ++j) e[j] = NAN;
+        int st = d_status(model, price[i], fs[i], K[i], T[i], r[i], q[i], flag[i]);
+        if (st != ORC_OK) continue;
+        qin a;
+        fill_in(&a, model, fs[i], K[i], T[i], r[i], q[i], flag[i]);
+        int ok;
+        qr s = q_implied_vol(&a, price[i], &ok);
+        if (ok <= 0) continue;
+        qr v = q_vega(&a, s);
+        qr dP[5];
+        q_price_partials(&a, s, dP);
+        const qr X[5] = {a.fs, a.K, a.T, a.r, a.q};
+        e[0] = (double)((qr)price[i] / v);
+        for (int j = 0; j < 5; ++j) e[1 + j] = (double)(-dP[j] * X[j] / v);
+        if (model != ORC_BSM) e[5] = 0.0;
+    }
+}
+
+/* The implicit-function gradient formula evaluated at a GIVEN volatility
+ * sigma (not at the root): d sigma/d P = 1/vega(sigma),
+ * d sigma/d X = -(dP/dX at fixed sigma)/vega(sigma) -- what an adjoint
+ * computes from a volatility solved elsewhere.  Rows of NaN where sigma is
+ * not finite and positive or the inputs are outside the model's domain;
+ * the price does not enter. */
+void orc_iv_grad_at_n(int model, int64_t n, const double *fs, const double *K,
+                      const double *T, const double *r, const double *q,
+                      const double *sigma, const int8_t *flag, double *grad)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        double *row = grad + 6 * i;
+        for (int j = 0; j < 6; ++j) row[j] = NAN;
+        if (!isfinite(sigma[i]) || !(sigma[i] > 0) || !isfinite(fs[i]) || !isfinite(K[i]) ||
+            !isfinite(T[i]) || !(fs[i] > 0) || !(K[i] > 0) || !(T[i] > 0))
+            continue;
+        qin a;
+        fill_in(&a, model, fs[i], K[i], T[i], r[i], q[i], flag[i]);
+        qr s = sigma[i];
+        qr v = q_vega(&a, s);
+        qr dP[5];
+        q_price_partials(&a, s, dP);
+        row[0] = (double)(1 / v);
+        for (int j = 0; j < 5; ++j) row[1 + j] = (double)(-dP[j] / v);
+        if (model != ORC_BSM) row[5] = 0.0;
+    }
+}
+
 /* Normalised Black function b(x, s, theta) =
  *   theta [ e^{x/2} Phi(theta (x/s + s/2)) - e^{-x/2} Phi(theta (x/s - s/2)) ]
  * (normalised coordinates of the paper's section 1: x = ln(F/K), s = sigma

@@ -59,6 +59,15 @@ MUTANTS = [
     ("normalised Black: e^{x/2} and e^{-x/2} swapped",
      "b = th * (expq(X / 2) * q_Phi(th * (h + t)) - expq(-X / 2) * q_Phi(th * (h - t)));",
      "b = th * (expq(-X / 2) * q_Phi(th * (h + t)) - expq(X / 2) * q_Phi(th * (h - t)));"),
+    ("relative sensitivity: price term without the price",
+     "e[0] = (double)((qr)price[i] / v);",
+     "e[0] = (double)(1 / v);"),
+    ("relative sensitivity: sign of the input terms",
+     "e[1 + j] = (double)(-dP[j] * X[j] / v);",
+     "e[1 + j] = (double)(dP[j] * X[j] / v);"),
+    ("gradient at a given sigma: 1/vega dropped from the input terms",
+     "row[1 + j] = (double)(-dP[j] / v);",
+     "row[1 + j] = (double)(-dP[j]);"),
     ("status: upper bound of a put is F",
      "double M = theta > 0 ? F : K;",
      "double M = theta > 0 ? F : F;"),

@@ -420,3 +420,123 @@ def test_iv_gradient_invariants(orc):
     euler = g[:, 0] * P + g[:, 1] * S + g[:, 2] * K
     scale = np.abs(g[:, 0] * P) + np.abs(g[:, 1] * S) + np.abs(g[:, 2] * K)
     assert np.all(np.abs(euler) <= 1e-10 * scale)
+
+
+# ------------------------------------------- relative sensitivities of the IV
+@pytest.mark.parametrize("model", MODELS)
+def test_iv_rel_sens_matches_log_differences(orc, model):
+    """X d sigma/d X against central differences of the exact root in ln X
+    (r and q: r d sigma/d r from absolute steps), normal-range prices."""
+    rng = np.random.default_rng(131 + MODELS.index(model))
+    S, K, T, r, q, sig, flag = _rand_quotes(rng, 120, model, zmax=2.5)
+    P = orc.price(model, S, K, T, r, q, sig, flag)
+    e = orc.iv_rel_sens(model, P, S, K, T, r, q, flag)
+
+    def IV(**kw):
+        a = dict(price=P, fs=S, K=K, T=T, r=r, q=q)
+        a.update(kw)
+        hi, lo, st = orc.implied_vol(model, a["price"], a["fs"], a["K"], a["T"], a["r"], a["q"],
+                                     flag, with_residual=True)
+        assert np.all(st == 0)
+        return hi.astype(np.longdouble) + lo
+
+    # steps in ln X as actually taken (the bumped inputs are rounded)
+    h = 1e-7
+    L = np.longdouble
+    for j, name in enumerate(("price", "fs", "K", "T")):
+        x = dict(price=P, fs=S, K=K, T=T)[name]
+        xp, xm = x * np.exp(h), x * np.exp(-h)
+        dl = np.log(xp.astype(L)) - np.log(xm.astype(L))
+        fd = ((IV(**{name: xp}) - IV(**{name: xm})) / dl).astype(float)
+        np.testing.assert_allclose(e[:, j], fd, rtol=1e-5, atol=1e-10, err_msg=name)
+    for j, name in ((4, "r"), (5, "q")):
+        x = dict(r=r, q=q)[name]
+        fd = (x * (IV(**{name: x + h}) - IV(**{name: x - h})) / (2 * h)).astype(float)
+        np.testing.assert_allclose(e[:, j], fd, rtol=1e-5, atol=1e-10, err_msg=name)
+    if model != "bsm":
+        assert np.all(e[:, 5] == 0)
+
+
+def _subnormal_price_cells(orc, r=0.0):
+    """Black-76 calls with F = 1, K = e^{-x}, T = 1 whose price lies below the
+    smallest normal binary64 number (deep out of the money): vega there is
+    below the binary64 range as well, and 1/vega overflows."""
+    xs = -np.linspace(5.0, 20.0, 61)
+    ss = np.exp(np.linspace(np.log(0.05), np.log(1.5), 61))
+    X, Sg = (a.ravel() for a in np.meshgrid(xs, ss, indexing="ij"))
+    K = np.exp(-X)
+    one = np.ones_like(X)
+    P = orc.price("black76", one, K, one, r * one, 0.0, Sg, 1)
+    keep = (P > 0) & (P < 2.2250738585072014e-308)
+    return X[keep], K[keep], P[keep]
+
+
+@pytest.mark.parametrize("r", [0.0, 0.03])
+def test_iv_rel_sens_subnormal_prices(orc, r):
+    """Where the price is subnormal, the sensitivities stay finite and obey
+    what the mathematics fixes:
+      * Euler: the IV is homogeneous of degree 0 in (price, F, K), so the
+        three signed relative sensitivities sum to zero;
+      * Black-76: sigma sqrt(T) depends on T only through the undiscounted
+        price P e^{rT}, so T dsigma/dT = -sigma/2 + r T e_P and
+        r dsigma/dr = r T e_P;
+      * e_P = P dsigma/dP = (b/b')/sqrt(T) at the root, with
+        b/b' = sqrt(pi/2) [erfcx(-(h+t)/sqrt2) - erfcx((t-h)/sqrt2)]
+        evaluated in mpmath at 60 digits."""
+    x, K, P = _subnormal_price_cells(orc, r)
+    assert len(x) >= 20
+    one = np.ones_like(x)
+    e = orc.iv_rel_sens("black76", P, one, K, one, r * one, 0.0, 1)
+    so, st = orc.implied_vol("black76", P, one, K, one, r * one, 0.0, 1)
+    assert np.all(st == 0) and np.all(np.isfinite(e[:, :5]))
+    # the binary64 gradient overflows here: the reason for this entry point
+    g = orc.iv_grad("black76", P, one, K, one, r * one, 0.0, 1)
+    assert np.all(~np.isfinite(g[:, 0]) | (np.abs(g[:, 0]) > 1e300))
+    scale = np.abs(e[:, 0]) + np.abs(e[:, 1]) + np.abs(e[:, 2])
+    assert np.all(np.abs(e[:, 0] + e[:, 1] + e[:, 2]) <= 1e-13 * scale)
+    np.testing.assert_allclose(e[:, 3], -so / 2 + r * e[:, 0], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(e[:, 4], r * e[:, 0], rtol=1e-12, atol=0)
+    mp.mp.dps = 60
+    try:
+        ref = []
+        for xi, si in zip(x, so):
+            X, s = mp.mpf(float(xi)), mp.mpf(float(si))
+            h, t = X / s, s / 2
+            erfcx = lambda z: mp.erfc(z) * mp.exp(z * z)
+            ref.append(float(mp.sqrt(mp.pi / 2) * (erfcx(-(h + t) / mp.sqrt(2)) -
+                                                   erfcx((t - h) / mp.sqrt(2)))))
+    finally:
+        mp.mp.dps = 15
+    np.testing.assert_allclose(e[:, 0], np.array(ref), rtol=1e-12)
+
+
+def test_iv_grad_at_given_sigma(orc):
+    """The gradient formula at an arbitrary sigma: d sigma/dP vega(sigma) = 1;
+    -d sigma/dX vega(sigma) = dP/dX at fixed sigma from central differences
+    of the pinned price; at the root it is the root's gradient."""
+    rng = np.random.default_rng(141)
+    for model in MODELS:
+        S, K, T, r, q, sig, flag = _rand_quotes(rng, 100, model, zmax=2.5)
+        g = orc.iv_grad_at(model, S, K, T, r, q, sig, flag)
+        vega = orc.greeks(model, S, K, T, r, q, sig, flag)["vega"]
+        np.testing.assert_allclose(g[:, 0] * vega, 1.0, rtol=1e-12)
+
+        def price(**kw):
+            a = dict(fs=S, K=K, T=T, r=r, q=q)
+            a.update(kw)
+            hi, lo = orc.price(model, a["fs"], a["K"], a["T"], a["r"], a["q"], sig, flag,
+                               with_residual=True)
+            return hi.astype(np.longdouble) + lo
+
+        names = ("fs", "K", "T", "r", "q") if model == "bsm" else ("fs", "K", "T", "r")
+        for j, name in enumerate(names, 1):
+            x = dict(fs=S, K=K, T=T, r=r, q=q)[name]
+            h = 1e-7 * (np.abs(x) if name in ("fs", "K", "T") else np.ones_like(x))
+            dP = ((price(**{name: x + h}) - price(**{name: x - h})) / (2 * h)).astype(float)
+            np.testing.assert_allclose(-g[:, j] * vega, dP, rtol=1e-6, atol=1e-9, err_msg=name)
+        P = orc.price(model, S, K, T, r, q, sig, flag)
+        so, st = orc.implied_vol(model, P, S, K, T, r, q, flag)
+        np.testing.assert_allclose(orc.iv_grad_at(model, S, K, T, r, q, so, flag),
+                                   orc.iv_grad(model, P, S, K, T, r, q, flag), rtol=1e-13)
+        assert np.all(np.isnan(orc.iv_grad_at(model, S[:3], K[:3], T[:3], r[:3], q[:3],
+                                              np.array([0.0, -1.0, np.nan]), flag[:3])))
