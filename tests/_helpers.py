@@ -43,16 +43,15 @@ def assemble_prices(wl: W.Flat) -> np.ndarray:
 
 
 def cond_abs(model, P, fs, K, T, r, q, flag) -> np.ndarray:
-    """sum_X |d sigma/d X| |X| over X in (price, S/F, K, T, r, q): the
+    """sum_X |X d sigma/d X| over X in (price, S/F, K, T, r, q): the
     first-order absolute change of the exact implied volatility when every
     input moves by one relative unit.  A binary64 implementation that rounds
     its inputs' derived quantities (forward, discount, log-moneyness,
-    normalised price) is accurate to a few ulps of this."""
-    g = oracle.iv_grad(model, P, fs, K, T, r, q, flag)
-    X = np.stack([P, np.broadcast_to(fs, P.shape), np.broadcast_to(K, P.shape),
-                  np.broadcast_to(T, P.shape), np.broadcast_to(r, P.shape),
-                  np.broadcast_to(q, P.shape)], 1)
-    return np.sum(np.abs(g * X), 1)
+    normalised price) is accurate to a few ulps of this.  The products are
+    formed by the oracle in binary128, so the sum stays finite also where
+    vega (and so 1/vega) leaves the binary64 range; NaN where the oracle
+    has no root."""
+    return np.sum(np.abs(oracle.iv_rel_sens(model, P, fs, K, T, r, q, flag)), 1)
 
 
 def iv_tolerance(solver, sigma_ref, cabs):
@@ -112,15 +111,113 @@ def compare_iv(model, solver, P, fs, K, T, r, q, flag, sig, st):
         cabs[idx] = cond_abs(model, P[idx], _take(fs, idx), _take(K, idx), _take(T, idx),
                              _take(r, idx), _take(q, idx), _take(flag, idx))
     tol = iv_tolerance(solver, so, cabs)
+    # a tolerance that is not a finite number would accept anything: such a
+    # quote is a failure of the comparison itself, never a pass
+    inf_tol = both_ok & ~np.isfinite(tol)
     err = np.abs(sig - so)
     val_bad = both_ok & ~(err <= tol)
     # NaN / zero conventions of the non-solvable statuses
     at = (st == 1) & (sto == 1)
     nan_bad = ((st >= 2) & (st <= 4) & ~np.isnan(sig)) | (at & (sig != 0.0))
     return dict(so=so, sto=sto, n_ok=int(both_ok.sum()), status_bad=np.where(st_bad)[0],
-                value_bad=np.where(val_bad)[0], nan_bad=np.where(nan_bad)[0],
+                value_bad=np.where(val_bad | inf_tol)[0], nan_bad=np.where(nan_bad)[0],
+                inf_tol=int(inf_tol.sum()),
                 ambiguous=int((amb & (sto != st)).sum()),
+                excluded=int((~both_ok).sum()),
                 max_ratio=float(np.max(err[both_ok] / tol[both_ok])) if both_ok.any() else 0.0)
+
+
+def greek_terms(model, S, K, T, r, q, sig, flag, P):
+    """Conditioning of the Greeks and of the gradient at sigma in binary64.
+    d1 and d2 carry an absolute error of about u (2 + |x| + |(r - q)T| +
+    |rT| + s^2)/s from the rounded arguments, which a normal density or tail
+    probability at d turns into a relative error of (|d| + 1) times that:
+    kappa = 1 + (|d1| + |d2| + 1)(2 + |x| + |(r-q)T| + |rT| + s^2)/s.
+    theta (and dP/dT) is a sum of terms of both signs, so its bound scales
+    with the sum of the terms' magnitudes (`theta_terms`), not its value.
+    Returns (kappa, theta_terms)."""
+    from scipy.special import ndtr
+    S, K, T, r, q, sig, flag, P = (np.asarray(a, dtype=np.float64) for a in
+                                   (S, K, T, r, q, sig, flag, P))
+    F, D = forward_discount(model, S, T, r, q)
+    Fx = S if model == "black76" else F
+    with np.errstate(all="ignore"):
+        s = sig * np.sqrt(T)
+        x = np.log(Fx / K)
+        d1 = x / s + 0.5 * s
+        d2 = d1 - s
+        carry = np.abs((r - q) * T) if model != "black76" else 0.0
+        kappa = 1.0 + (np.abs(d1) + np.abs(d2) + 1.0) * (2.0 + np.abs(x) + carry +
+                                                         np.abs(r * T) + s * s) / s
+        pdf1 = np.exp(-0.5 * d1 * d1) / np.sqrt(2 * np.pi)
+        Dq = np.exp(-q * T) if model == "bsm" else np.ones_like(T)
+        if model == "black76":
+            theta_terms = np.abs(r * P) + D * Fx * pdf1 * sig / (2 * np.sqrt(T))
+        else:
+            qq = q if model == "bsm" else 0.0
+            theta_terms = (S * Dq * pdf1 * sig / (2 * np.sqrt(T)) +
+                           np.abs(r * K * D * ndtr(flag * d2)) + np.abs(qq * S * Dq * ndtr(flag * d1)))
+    return kappa, theta_terms
+
+
+GREEK_NAMES = ("delta", "gamma", "vega", "theta", "rho")
+
+
+def greeks_bad(model, S, K, T, r, q, sig, flag, got, ref=None, P=None, ulps=64):
+    """Element-wise check of the five Greeks at volatility `sig` (got: dict of
+    arrays) against the oracle's binary128 Greeks at the same `sig`: every
+    element within ulps u kappa of the value (of theta's terms for theta).
+    Returns {name: indices of failures} and the largest error/tolerance."""
+    if ref is None:
+        ref = oracle.greeks(model, S, K, T, r, q, sig, flag)
+    if P is None:
+        P = oracle.price(model, S, K, T, r, q, sig, flag)
+    kappa, theta_terms = greek_terms(model, S, K, T, r, q, sig, flag, P)
+    out, worst = {}, 0.0
+    for name in GREEK_NAMES:
+        a, b = np.asarray(got[name]), ref[name]
+        scale = theta_terms if name == "theta" else np.abs(b)
+        tol = ulps * U * kappa * scale + 1e-300
+        with np.errstate(invalid="ignore"):
+            bad = ~(np.abs(a - b) <= tol)
+            r_ = np.abs(a - b) / tol
+        out[name] = np.where(bad)[0]
+        if np.any(np.isfinite(r_)):
+            worst = max(worst, float(np.nanmax(r_)))
+    return out, worst
+
+
+GRAD_NAMES = ("price", "fs", "K", "T", "r", "q")
+
+
+def grad_bad(model, S, K, T, r, q, sig, flag, got, w=None, P=None, ulps=64):
+    """Element-wise check of the implied-volatility gradient evaluated at
+    `sig` (got: (n, 6) array of w * d sigma/d X) against the oracle's
+    binary128 gradient formula at the same sigma: within ulps u kappa of the
+    value (dsigma/dT: of |w| theta's terms / vega).  Elements whose oracle
+    value is not a finite binary64 number are returned apart.  Returns
+    ({name: failures}, worst ratio, number of non-finite reference values)."""
+    n = len(np.atleast_1d(sig))
+    w = np.ones(n) if w is None else np.asarray(w)
+    go = oracle.iv_grad_at(model, S, K, T, r, q, sig, flag) * w[:, None]
+    if P is None:
+        P = oracle.price(model, S, K, T, r, q, sig, flag)
+    kappa, theta_terms = greek_terms(model, S, K, T, r, q, sig, flag, P)
+    vega = np.abs(oracle.greeks(model, S, K, T, r, q, sig, flag)["vega"])
+    out, worst, n_nonfinite = {}, 0.0, 0
+    for j, name in enumerate(GRAD_NAMES):
+        a, b = np.asarray(got[:, j]), go[:, j]
+        fin = np.isfinite(b) & (np.abs(b) < 1e300)
+        n_nonfinite += int((~fin).sum())
+        with np.errstate(all="ignore"):
+            scale = np.abs(w) * theta_terms / vega if name == "T" else np.abs(b)
+            tol = ulps * U * kappa * scale + 1e-300
+            bad = fin & ~(np.abs(a - b) <= tol)
+            r_ = np.where(fin, np.abs(a - b) / tol, np.nan)
+        out[name] = np.where(bad)[0]
+        if np.any(np.isfinite(r_)):
+            worst = max(worst, float(np.nanmax(r_)))
+    return out, worst, n_nonfinite
 
 
 def _take(a, idx):

@@ -63,6 +63,9 @@ def measure(fv, torch, nx=160, ns=160):
     ca = cond_abs("black76", P[idx], one[idx], K[idx], one[idx], zero[idx], 0.0, calls[idx])
     tol[idx] = iv_tolerance("lbr", so[idx], ca)
     tol_h[idx] = iv_tolerance("halley", so[idx], ca)
+    # a tolerance that is not finite would accept any value
+    res["inf_tol"] = int(np.sum(~np.isfinite(tol[idx])) + np.sum(~np.isfinite(tol_h[idx])))
+    res["subnormal_price_cells"] = int(np.sum(P[idx] < 2.2250738585072014e-308))
     for solver, tl in (("lbr", tol), ("halley", tol_h)):
         sg, sst = fv.implied_vol("black76", d(P[idx]), d(one[idx]), d(K[idx]), d(one[idx]),
                                  d(zero[idx]), flag=d(calls[idx], torch.int8), solver=solver)
@@ -118,6 +121,10 @@ def main():
                   " | ".join("-" if not np.isfinite(v) else "%.3g" % v for v in t[i]) + " |")
         allv = res[key][np.isfinite(res[key])]
         print("\nmax %.4g u, median %.3g u over %d cells" % (allv.max(), np.median(allv), allv.size))
+        if key == "b":
+            print("; solvable cells with a price below the normal binary64 range: %d; "
+                  "cells with a non-finite parity tolerance: %d"
+                  % (res["subnormal_price_cells"], res["inf_tol"]))
         if key != "b":
             rr = res[key + "_ratio"]
             rr = rr[np.isfinite(rr)]

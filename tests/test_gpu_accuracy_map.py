@@ -24,6 +24,10 @@ def test_plane_within_bounds(fv):
     xs, ss, res, ok = AM.measure(fv, torch, nx, ns)
     _, _, x, s = AM.plane(nx, ns)
     assert ok.sum() > 0.6 * ok.size
+    # every solvable cell is compared against a finite tolerance, including
+    # the cells whose price lies below the normal binary64 range
+    assert res["inf_tol"] == 0
+    assert res["subnormal_price_cells"] > 0
     # b: rounding of h = x/s and of the exp argument, amplified by h^2 + t^2
     h, t = x / s, 0.5 * s
     bound = 16.0 * (1.0 + h * h + t * t)
@@ -33,6 +37,9 @@ def test_plane_within_bounds(fv):
     for solver in ("lbr", "halley"):
         r = res[solver + "_ratio"]
         assert np.nanmax(r) <= 1.0, (solver, np.nanmax(r))
+        # solved cells are compared; no solvable cell is left unsolved except
+        # by a boundary-ambiguous status (checked below)
+        assert np.all(np.isfinite(r[ok]) | np.isin(np.where(ok)[0], res[solver + "_status_mismatch"]))
         mis = res[solver + "_status_mismatch"]
         if len(mis):
             K = np.exp(-x[mis])
