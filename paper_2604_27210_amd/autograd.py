@@ -43,15 +43,29 @@ class IVFunction(torch.autograd.Function):
         args = [v.item() if s else v.detach() for v, s in zip((price, fs, K, T, r, q), ctx.scalar)]
         g = api.implied_vol_backward(ctx.model, args[0], args[1], args[2], args[3], args[4],
                                      sig, g_sig.contiguous(), flag=ctx.flag, q=args[5])
-        outs = []
-        for name, s, need in zip(("price", "fs", "K", "T", "r", "q"), ctx.scalar,
-                                 ctx.needs_input_grad[:6]):
-            outs.append(g[name] if (need and not s) else None)
-        return (*outs, None, None, None, None)
+        return (*_input_grads(g, ("price", "fs", "K", "T", "r", "q"), ctx.scalar,
+                              ctx.needs_input_grad[:6], (price, fs, K, T, r, q)),
+                None, None, None, None)
 
 
 def _d(v):
     return v.detach() if isinstance(v, torch.Tensor) else v
+
+
+def _input_grads(g, names, scalar, needs, saved):
+    """Gradient of each input from the per-quote adjoint rows g[name]: the row
+    itself for a per-quote tensor; for a 0-dim tensor broadcast to every
+    quote (a shared r or T, say) the sum of the row over the quotes, with the
+    input's dtype and device; None where no gradient is needed."""
+    outs = []
+    for name, s, need, v in zip(names, scalar, needs, saved):
+        if not need:
+            outs.append(None)
+        elif s:
+            outs.append(g[name].sum().to(dtype=v.dtype, device=v.device).reshape(v.shape))
+        else:
+            outs.append(g[name])
+    return outs
 
 
 def implied_vol_autograd(model, price, fs, K, T, r, flag="c", q=None, solver="lbr",
@@ -83,11 +97,8 @@ class PriceFunction(torch.autograd.Function):
         a = [v.item() if s else v.detach() for v, s in zip(saved, ctx.scalar)]
         g = api.price_backward(ctx.model, a[0], a[1], a[2], a[3], a[5], g_p.contiguous(),
                                flag=ctx.flag, q=a[4])
-        outs = []
-        for name, s, need in zip(("fs", "K", "T", "r", "q", "sigma"), ctx.scalar,
-                                 ctx.needs_input_grad[:6]):
-            outs.append(g[name] if (need and not s) else None)
-        return (*outs, None, None)
+        return (*_input_grads(g, ("fs", "K", "T", "r", "q", "sigma"), ctx.scalar,
+                              ctx.needs_input_grad[:6], saved), None, None)
 
 
 def price_autograd(model, fs, K, T, r, sigma, flag="c", q=None):

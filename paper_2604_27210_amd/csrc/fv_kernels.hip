@@ -264,7 +264,8 @@ __attribute__((amdgpu_waves_per_eu(FV_WAVES(GREEKS)))) void k_iv_halley(KQuotes 
     const double qy = MODEL == fv::kBlackScholesMerton ? ld(q.q, i) : 0.0;
     const int th = ldflag(q, i);
     const Reduced rd = fv::reduce_quote(MODEL, P, fs, K, T, r, qy, th);
-    const double s = fv::bisection_solve(rd.x, rd.beta, rd.bmax, queue[j].lo, queue[j].hi, kBisectTol);
+    const double s =
+        fv::bisection_solve(rd.x, rd.beta, rd.bmax, rd.lnb, queue[j].lo, queue[j].hi, kBisectTol);
     const double sg = s / rd.sqrtT;
     sig_out[i] = sg;
     if (st_out) st_out[i] = fv::kQOk;
@@ -587,7 +588,7 @@ __attribute__((amdgpu_waves_per_eu(FV_CHAINS_WAVES_PER_EU))) void k_iv_chains(
           fv::HalleyState hs = fv::halley_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kHalleySteps);
           double s = hs.s;
           if (!hs.converged)
-            s = fv::bisection_solve(rd.x, rd.beta, rd.bmax, hs.lo, hs.hi, kBisectTol);
+            s = fv::bisection_solve(rd.x, rd.beta, rd.bmax, rd.lnb, hs.lo, hs.hi, kBisectTol);
           sg = s / rd.sqrtT;
         }
       }

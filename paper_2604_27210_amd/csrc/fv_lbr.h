@@ -321,44 +321,66 @@ struct HalleyState {
   bool converged;
 };
 
-// Brenner-Subrahmanyam start s0 = sqrt(2 pi) beta (the at-the-money
-// approximation b(0, s) ~ s/sqrt(2 pi)), then at most `steps` Halley steps on
-// the direct residual b(s) - beta: step = nu/(1 + eta nu/2), nu = (beta - b)/b',
-// eta = b''/b'.  Safeguards (the paper does not spell its own out):
+// Normalised prices below this (2^-960) are solved on the logarithmic
+// residual ln b(s) - ln beta: there beta, and b near the root, are at or
+// below the edge of the normal binary64 range, keep few significant bits,
+// and the direct residual b - beta and its relative test lose their meaning.
+constexpr double kLnBetaLogResidual = -665.4;  // ln 2^-960
+
+// ln b(x, s) from an evaluation: ln b' + ln(b/b') in the difference form
+// (both parts stay in the normal range however small b is), ln b in the
+// complement form (where b >= 0.3 b_max).
+__host__ __device__ inline double ln_nb(const NBlack& nb) {
+  return nb.form == kFormDifference ? nb.lnbp + flog(nb.ratio) : flog(nb.b);
+}
+
+// One Halley step from s; `res` receives the residual at s and `st` the
+// bracket its sign fixes.  Two residuals:
+//  * direct (beta >= 2^-960): g = b(s) - beta, step = nu/(1 + eta nu/2),
+//    nu = -g/b', eta = b''/b';
+//  * logarithmic (beta < 2^-960): g = ln b(s) - ln beta, g' = b'/b = lambda,
+//    g''/g' = eta - lambda, step = nu/(1 + (eta - lambda) nu/2), nu = -g/lambda.
+// Safeguards (the paper does not spell its own out):
 //  * far below the root of an out-of-the-money quote b(s) behaves like
-//    C s^3 exp(-x^2/(2 s^2)), so the curvature term makes the Halley step
-//    crawl (step ~ 2 s^3/x^2).  When the residual is negative and the Halley
-//    factor 1/(1 + eta nu/2) has dropped below 1/2, the step is a Newton step
-//    on ln b - ln beta in u = 1/s^2, where ln b is nearly linear (or, when
-//    b underflowed, to max(2 s, |x|/sqrt(-2 ln beta)), the root of the
-//    leading-order form);
+//    C s^3 exp(-x^2/(2 s^2)), so on the direct residual the curvature term
+//    makes the Halley step crawl (step ~ 2 s^3/x^2).  When the residual is
+//    negative and the Halley factor 1/(1 + eta nu/2) has dropped below 1/2,
+//    the step is a Newton step on ln b - ln beta in u = 1/s^2, where ln b is
+//    nearly linear (or, when b underflowed, to max(2 s, |x|/sqrt(-2 ln beta)),
+//    the root of the leading-order form);
 //  * a bracket [lo, hi] from the sign of the residual keeps every iterate
 //    inside; a step that would leave it bisects instead (geometrically).
-// A lane stops as soon as its step is below 1e-14 s (the root in binary64):
-// a wave whose lanes have all converged leaves the loop early.
-// Converged: last |step| <= 1e-10 s and |b - beta| <= 1e-9 beta.
 __host__ __device__ __attribute__((always_inline)) inline double halley_step(
-    double x, double beta, double bmax, double ln_beta, double s, HalleyState& st,
+    double x, double beta, double bmax, double ln_beta, bool logres, double s, HalleyState& st,
     double& res) {
   const NBlack nb = normalised_black(x, s, bmax);
-  res = nb.b - beta;
-  if (res < 0.0) st.lo = s; else st.hi = s;
-  const double nu = -res * rcp(nb.bp);
   const double is0 = rcp_lo(s);
   const double eta = x * x * is0 * is0 * is0 - 0.25 * s;  // b''/b'
-  const double hf = rcp_lo(1.0 + 0.5 * eta * nu);
-  double sn = s + nu * hf;
-  if (res < 0.0 && !(hf >= 0.5) && x < 0.0) {
-    // Newton step on ln b - ln beta in u = 1/s^2, where ln b is close to
-    // linear: d ln b/du = -(b'/b) s^3/2.  If b underflowed (to zero or a
-    // denormal) or the step is unusable, the root of the leading-order form
-    // b ~ exp(-x^2/(2 s^2)), but at least 2 s.
-    double un = -1.0;
-    if (nb.b > 1e-290) {
-      const double dLdu = -0.5 * nb.bp * rcp_lo(nb.b) * s * s * s;
-      un = fma(fdiv_lo(ln_beta - flog(nb.b), dLdu), 1.0, is0 * is0);
+  double sn;
+  if (logres) {
+    res = ln_nb(nb) - ln_beta;
+    if (res < 0.0) st.lo = s; else st.hi = s;
+    const double lam = rcp(nb.ratio);  // b'/b
+    const double nu = -res * nb.ratio;
+    sn = s + nu * rcp_lo(1.0 + 0.5 * (eta - lam) * nu);
+  } else {
+    res = nb.b - beta;
+    if (res < 0.0) st.lo = s; else st.hi = s;
+    const double nu = -res * rcp(nb.bp);
+    const double hf = rcp_lo(1.0 + 0.5 * eta * nu);
+    sn = s + nu * hf;
+    if (res < 0.0 && !(hf >= 0.5) && x < 0.0) {
+      // Newton step on ln b - ln beta in u = 1/s^2, where ln b is close to
+      // linear: d ln b/du = -(b'/b) s^3/2.  If b underflowed (to zero or a
+      // denormal) or the step is unusable, the root of the leading-order form
+      // b ~ exp(-x^2/(2 s^2)), but at least 2 s.
+      double un = -1.0;
+      if (nb.b > 1e-290) {
+        const double dLdu = -0.5 * nb.bp * rcp_lo(nb.b) * s * s * s;
+        un = fma(fdiv_lo(ln_beta - flog(nb.b), dLdu), 1.0, is0 * is0);
+      }
+      sn = (un > 0.0 && un < 1e300) ? rsqrt(un) : fmax(2.0 * s, -x * rsqrt(-2.0 * ln_beta));
     }
-    sn = (un > 0.0 && un < 1e300) ? rsqrt(un) : fmax(2.0 * s, -x * rsqrt(-2.0 * ln_beta));
   }
   // inclusive test: at the root the step rounds to 0 and s is a bound
   if (!(sn >= st.lo && sn <= st.hi)) {
@@ -369,35 +391,51 @@ __host__ __device__ __attribute__((always_inline)) inline double halley_step(
   return sn;
 }
 
+// Start: Brenner-Subrahmanyam s0 = sqrt(2 pi) beta (the at-the-money
+// approximation b(0, s) ~ s/sqrt(2 pi)); on the logarithmic residual away
+// from the money the root of the leading-order form
+// ln b ~ -x^2/(2 s^2), s0 = |x|/sqrt(-2 ln beta).  Then at most `steps`
+// Halley steps.  A lane stops as soon as its step is below 1e-14 s (the
+// root in binary64): a wave whose lanes have all converged leaves the loop
+// early.  Converged: last |step| <= 1e-10 s, the residual within 1e-9
+// relative (|b - beta| <= 1e-9 beta, or |ln b - ln beta| <= 1e-9), and a
+// positive finite s.
 __host__ __device__ __attribute__((always_inline)) inline HalleyState halley_solve(
     double x, double beta, double bmax, double ln_beta, int steps) {
   HalleyState st;
   st.lo = 0.0;
   st.hi = 1e300;
-  double s = kSqrt2Pi * beta;
+  const bool logres = ln_beta < kLnBetaLogResidual;
+  double s = (logres && x < 0.0) ? -x * rsqrt(-2.0 * ln_beta) : kSqrt2Pi * beta;
   double ds = 0.0, res = 0.0;
   for (int k = 0; k < steps; ++k) {
-    const double sn = halley_step(x, beta, bmax, ln_beta, s, st, res);
+    const double sn = halley_step(x, beta, bmax, ln_beta, logres, s, st, res);
     ds = sn - s;
     s = sn;
     if (fabs(ds) <= 1e-14 * s) break;
   }
   st.s = s;
-  st.converged = fabs(ds) <= 1e-10 * s && fabs(res) <= 1e-9 * beta;
+  st.converged = fabs(ds) <= 1e-10 * s && fabs(res) <= (logres ? 1e-9 : 1e-9 * beta) &&
+                 s > 0.0 && __builtin_isfinite(s);
   return st;
 }
 
-__host__ __device__ inline double bisection_solve(double x, double beta, double bmax, double lo,
-                                                  double hi, double rel_tol) {
+// Bisection on ln s inside [lo, hi] to rel_tol, comparing b with beta (in
+// logarithms below 2^-960, as the Halley residual does).
+__host__ __device__ inline double bisection_solve(double x, double beta, double bmax,
+                                                  double ln_beta, double lo, double hi,
+                                                  double rel_tol) {
   // an end the caller's bracket did not fix: far below any root, and far
   // above it (b_max - b(s) < b_max 1e-16 once s exceeds ~20 + |x|/10)
   if (!(lo > 0.0)) lo = 1e-300;
   if (!(hi < 1e300)) hi = 1e3;
+  const bool logres = ln_beta < kLnBetaLogResidual;
   // geometric midpoints as sqrt(lo) sqrt(hi): lo hi may underflow
   for (int k = 0; k < 200 && hi - lo > rel_tol * hi; ++k) {
     const double mid = sqrt(lo) * sqrt(hi);
     const NBlack nb = normalised_black(x, mid, bmax);
-    if (nb.b < beta) lo = mid; else hi = mid;
+    const bool below = logres ? ln_nb(nb) < ln_beta : nb.b < beta;
+    if (below) lo = mid; else hi = mid;
   }
   return sqrt(lo) * sqrt(hi);
 }

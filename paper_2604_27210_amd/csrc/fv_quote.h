@@ -83,6 +83,14 @@ __host__ __device__ inline double forward_of(int model, double fs, double T, dou
   return fs * (model == kBlackScholesMerton ? fexp_carry(r, q, T) : fexp_prod(r, T));
 }
 
+// ln(F/K) from the ratio while F/K is a normal number, else from the two
+// logarithms (|ln(F/K)| beyond about 708, or an operand the refined
+// reciprocal cannot take: the comparisons fail on a NaN ratio).
+__host__ __device__ inline double log_moneyness(double F, double K) {
+  const double fk = F * rcp(K);
+  return (fk > kDblMin && fk < 0x1p1023) ? flog(fk) : flog(F) - flog(K);
+}
+
 __host__ __device__ inline Reduced reduce_quote(int model, double price, double fs, double K,
                                                 double T, double r, double q, int theta) {
   Reduced o;
@@ -106,14 +114,7 @@ __host__ __device__ inline Reduced reduce_quote(int model, double price, double 
   if (Pu == I) { o.status = kQAtIntrinsic; return o; }
   if (Pu >= M) { o.status = kQAboveMax; return o; }
   const int th = (I > 0.0) ? -theta : theta;  // in the money: parity to OTM
-  // ln(F/K) from the ratio, or from the two logarithms where F/K leaves the
-  // normal range (|ln(F/K)| beyond about 708)
-  const double fk = F * rcp(K);
-  double lx;
-  if (fk > kDblMin && fk < 0x1p1023)
-    lx = flog(fk);
-  else
-    lx = flog(F) - flog(K);
+  const double lx = log_moneyness(F, K);
   o.x = th > 0 ? lx : -lx;
   // 1/sqrt(F K) as two factors: F K itself leaves the binary64 range once F
   // and K are beyond about 1e+-154, while the normalised quantities do not
@@ -156,7 +157,7 @@ __host__ __device__ inline BsTerms bs_terms(double F, double K, double D, double
   BsTerms c;
   c.sqT = sqrt_pos(T);
   c.s = sigma * c.sqT;
-  c.d1 = flog(F / K) / c.s + 0.5 * c.s;
+  c.d1 = log_moneyness(F, K) / c.s + 0.5 * c.s;
   c.d2 = c.d1 - c.s;
   c.N1 = norm_cdf(theta * c.d1);
   c.N2 = norm_cdf(theta * c.d2);
@@ -248,7 +249,7 @@ __host__ __device__ inline IvGrad iv_gradient(int model, double fs, double K, do
 // option obtained from the out-of-the-money call by parity.
 __host__ __device__ inline double price_at(double F, double K, double D, double sigma,
                                            double sqrtT, int theta) {
-  const double lx = flog(F / K);
+  const double lx = log_moneyness(F, K);
   // out-of-the-money side: x_otm <= 0
   const bool itm = theta * lx > 0.0;
   const double x = -fabs(lx);
