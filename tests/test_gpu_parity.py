@@ -623,3 +623,48 @@ def test_price_fuzz_extreme_ranges(fv, model):
     bad = ~(np.abs(p - po) <= tol)
     print("price-fuzz/%s: max err/tol %.3g" % (model, np.nanmax(np.abs(p - po) / tol)))
     assert bad.sum() == 0, (np.where(bad)[0][:5], p[bad][:5], po[bad][:5])
+
+
+@pytest.mark.parametrize("solver", ["lbr", "halley"])
+def test_subnormal_prices(fv, solver):
+    """Out-of-the-money quotes whose price is below the normal binary64 range
+    (the accuracy plane's subnormal cells, spread over three models and both
+    flags by scaling), and a normalised price that underflows to zero: each
+    solved to the oracle's root within the parity tolerance, which is finite
+    for every one of them."""
+    xs = np.concatenate([[0.0], -np.logspace(-4, np.log10(20.0), 159)])
+    ss = np.logspace(-3, np.log10(8.0), 160)
+    X, S = (a.ravel() for a in np.meshgrid(xs, ss, indexing="ij"))
+    one = np.ones_like(X)
+    P = oracle.price("black76", one, np.exp(-X), one, 0 * one, 0.0, S, 1)
+    keep = (P > 0) & (P < 2.2250738585072014e-308)
+    X, S = X[keep], S[keep]
+    m = len(X)
+    assert m >= 20
+    rng = np.random.default_rng(77)
+    for model in ("black76", "bs", "bsm"):
+        fl = np.where(rng.random(m) < 0.5, 1, -1).astype(np.int8)
+        T = rng.uniform(0.5, 2.0, m)
+        r = rng.uniform(0.0, 0.05, m) if model != "black76" else np.zeros(m)
+        q = rng.uniform(0.0, 0.03, m) if model == "bsm" else np.zeros(m)
+        Sx = np.exp(rng.uniform(np.log(1.0), np.log(1e4), m))
+        F, _ = forward_discount(model, Sx, T, r, q)
+        # out of the money at |x| for either flag
+        K = F * np.exp(-fl * X)
+        sig = S / np.sqrt(T)
+        Pq = oracle.price(model, Sx, K, T, r, q, sig, fl)
+        if model == "black76":
+            Sx = np.append(Sx, 1e300)
+            K = np.append(K, 1e301)
+            T, r, q = np.append(T, 1.0), np.append(r, 0.0), np.append(q, 0.0)
+            fl = np.append(fl, np.int8(1))
+            Pq = np.append(Pq, 1e-300)
+        s, st = fv.implied_vol(model, dev(Pq), dev(Sx), dev(K), dev(T), dev(r),
+                               flag=dev(fl, torch.int8), q=dev(q) if model == "bsm" else None,
+                               solver=solver)
+        res = compare_iv(model, solver, Pq, Sx, K, T, r, q, fl, host(s), host(st))
+        _report("subnormal/%s/%s" % (model, solver), res)
+        assert res["inf_tol"] == 0
+        assert len(res["status_bad"]) == 0 and len(res["value_bad"]) == 0, (
+            res["value_bad"][:5], res["max_ratio"])
+        assert res["n_ok"] >= 0.9 * len(Pq)
