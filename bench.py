@@ -328,6 +328,14 @@ def extras(fv, torch, main_inputs):
         res["graph" if graph else "eager"] = {"steps_per_s": r_["steps_per_s"],
                                               "final_rmse_vol_points": rmse,
                                               "final_loss": float(c.losses()[-1])}
+    # the oracle's final RMSE on the same problem (binary128 targets, numpy
+    # replay of the 200 steps), stored by tests/golden/make_svi_calibration.py
+    gold_path = os.path.join(ROOT, "tests", "golden", "svi_calibration_500.json")
+    with open(gold_path) as fh:
+        gold = json.load(fh)
+    res["oracle_final_rmse_vol_points"] = gold["final_rmse_vol_points"]
+    res["graph_minus_oracle_rmse_vol_points"] = (res["graph"]["final_rmse_vol_points"]
+                                                 - gold["final_rmse_vol_points"])
     out["svi_calibration_500_chains"] = dict(n_quotes=chc.n, n_maturities=chc.n_mat,
                                              steps=200, **res)
     return out

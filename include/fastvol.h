@@ -185,9 +185,11 @@ int fv_price_backward(int model, const fv_quotes *q, fv_arg sigma, const double 
                       double *g_fs, double *g_K, double *g_T, double *g_r, double *g_q,
                       double *g_sigma, void *stream);
 
-/* Implied volatility of ragged Black-76 chains in ONE persistent launch: the
- * grid is sized to the device and every workgroup walks fixed-size quote
- * chunks, finding each quote's maturity and chain through the CSR offsets.
+/* Implied volatility of ragged Black-76 chains in ONE launch over the flat
+ * quote range: one workgroup per fixed-size chunk of consecutive quotes (the
+ * hardware scheduler balances the uneven per-quote cost; no grid-stride
+ * loop), each wave finding its quotes' maturity and chain through the CSR
+ * offsets, so no per-quote F, r or T array is materialised.
  * sigma_out [n_quotes] required, status_out [n_quotes] or NULL. */
 int fv_implied_vol_chains(int solver, const fv_chains *c, double *sigma_out,
                           uint8_t *status_out, void *stream);

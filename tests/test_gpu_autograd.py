@@ -203,14 +203,19 @@ def test_scalar_inputs_get_summed_gradients(fv):
         rs = torch.tensor(r0, dtype=torch.float64, device=where, requires_grad=True)
         ins2 = [dev(P, grad=True), dev(wl.fs), dev(wl.K), Ts, rs, dev(wl.q)]
         sig2, st2 = fv.implied_vol_autograd("bsm", *ins2[:5], flag=fl, q=ins2[5])
-        assert torch.equal(sig2.detach(), sig.detach()) and torch.equal(st2, st)
+        # the same solve (unsolved quotes are NaN in both, which torch.equal
+        # would count as a difference)
+        assert torch.equal(st2, st)
+        assert torch.equal(torch.isnan(sig2), torch.isnan(sig))
+        ok = ~torch.isnan(sig)
+        assert torch.allclose(sig2.detach()[ok], sig.detach()[ok], rtol=1e-15, atol=0.0)
         (w * sig2).sum().backward()
         assert Ts.grad is not None and rs.grad is not None
         assert Ts.grad.device.type == where and Ts.grad.dim() == 0
         for t0, t in ((ins[3], Ts), (ins[4], rs)):
             ref = t0.grad.sum().item()
             assert abs(t.grad.item() - ref) <= 1e-12 * t0.grad.abs().sum().item(), (where, t.grad, ref)
-        assert torch.equal(ins2[0].grad, ins[0].grad)
+        assert torch.allclose(ins2[0].grad, ins[0].grad, rtol=1e-13, atol=0.0)
     # the price adjoint: a shared sigma and r
     sg = torch.tensor(0.3, dtype=torch.float64, device="cuda", requires_grad=True)
     rs = torch.tensor(r0, dtype=torch.float64, device="cuda", requires_grad=True)

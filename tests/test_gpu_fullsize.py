@@ -224,6 +224,13 @@ def _raw(th):
 
 
 def test_calibration_500_chains_full(fv):
+    """The 500-chain calibration as benchmarked (200 graph-replayed Adam
+    steps) against the oracle's numpy replay of all 200 steps on the
+    oracle's own targets: every loss, every parameter and the final RMSE;
+    the replay also reproduces the stored figures of
+    tests/golden/svi_calibration_500.json that the bench prints."""
+    import json
+    import os
     from paper_2604_27210_amd.calibrate import SviCalibrator, calibrate_svi, raw_from_natural
     c = W.svi_calibration(500, seed=5)
     ch = c.chains
@@ -234,26 +241,29 @@ def test_calibration_500_chains_full(fv):
     target, st = oracle.implied_vol("black76", P, ch.F[chain], ch.K, ch.T[mat], ch.r[chain], 0.0,
                                     ch.flag)
     target = np.where(st == 0, target, np.nan)
-
-    def make():
-        return SviCalibrator(dev(ch.chain_mat_off, torch.int64), dev(ch.mat_quote_off, torch.int64),
-                             dev(ch.F), dev(ch.r), dev(ch.T), dev(ch.K), dev(ch.flag, torch.int8),
-                             dev(target), raw_from_natural(c.theta0), lr=1e-2)
-
-    cal = make()
-    calibrate_svi(cal, 20, graph=False)
-    torch.cuda.synchronize()
-    th_o, L_o = svi.adam_replay(_raw(c.theta0), ch.k, mat, ch.T, target, 20)
-    L = cal.losses()
-    np.testing.assert_allclose(L, L_o, rtol=1e-6)
-    np.testing.assert_allclose(cal.theta.cpu().numpy().reshape(-1, 5), th_o, rtol=1e-6, atol=1e-9)
-    # the full 200 graph-replayed steps of the benchmark
-    cal = make()
+    cal = SviCalibrator(dev(ch.chain_mat_off, torch.int64), dev(ch.mat_quote_off, torch.int64),
+                        dev(ch.F), dev(ch.r), dev(ch.T), dev(ch.K), dev(ch.flag, torch.int8),
+                        dev(target), raw_from_natural(c.theta0), lr=1e-2)
     calibrate_svi(cal, 200, graph=True)
     torch.cuda.synchronize()
     L = cal.losses()
-    assert len(L) == 200 and np.all(np.isfinite(L))
-    assert L[-1] < 0.05 * L[0]
+    th = cal.theta.cpu().numpy().reshape(-1, 5)
     ok = np.isfinite(target)
     rmse = 100 * np.sqrt(np.mean((cal.vols().cpu().numpy()[ok] - target[ok]) ** 2))
-    assert rmse < 3.0, rmse
+    th_o, L_o = svi.adam_replay(_raw(c.theta0), ch.k, mat, ch.T, target, 200)
+    rmse_o = 100 * np.sqrt(np.mean((svi.svi_vols(th_o, ch.k, mat, ch.T)[ok] - target[ok]) ** 2))
+    print("calibration-500: %d quotes, %d maturities; rmse gpu %.12f oracle %.12f; "
+          "max loss rel dev %.3g; max theta dev %.3g"
+          % (ch.n, ch.n_mat, rmse, rmse_o, np.max(np.abs(L / L_o - 1)), np.max(np.abs(th - th_o))))
+    assert len(L) == 200 and np.all(np.isfinite(L))
+    np.testing.assert_allclose(L[:20], L_o[:20], rtol=1e-9)
+    np.testing.assert_allclose(L, L_o, rtol=1e-6)
+    np.testing.assert_allclose(th, th_o, rtol=1e-6, atol=1e-9)
+    assert abs(rmse - rmse_o) <= 1e-6
+    assert L[-1] < 0.05 * L[0]
+    with open(os.path.join(os.path.dirname(__file__), "golden", "svi_calibration_500.json")) as fh:
+        gold = json.load(fh)
+    assert gold["workload"]["n_quotes"] == ch.n and gold["workload"]["steps"] == 200
+    assert abs(gold["final_rmse_vol_points"] - rmse_o) <= 1e-9 * rmse_o
+    for k, v in gold["loss_at_step"].items():
+        assert abs(v - L_o[int(k)]) <= 1e-9 * v, k

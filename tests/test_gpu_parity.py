@@ -231,9 +231,12 @@ def _ncdf(x):
 def test_fused_greeks_match_separate_call_and_oracle(fv, solver):
     """The Greeks fused into the solve, element by element: against the
     oracle's binary128 Greeks at the solved sigma (within 64 u kappa), and
-    bitwise equal to fv_greeks at that sigma (Black-Scholes-Merton's Greeks
-    do not use the price, so both launches evaluate the same expressions);
-    NaN wherever the status is not OK."""
+    against fv_greeks at that sigma (Black-Scholes-Merton's Greeks do not use
+    the price, so both launches evaluate the same expressions): delta, gamma,
+    vega and rho, which are products, bitwise; theta, a sum of three terms
+    whose contraction into fused multiply-adds each kernel's compiler decides
+    on its own, within 4 u of the sum of the terms' magnitudes.  NaN wherever
+    the status is not OK."""
     wl = W.bsm_diff(50_000, seed=4)
     P = assemble_prices(wl)
     sig, st, gk = run_iv(fv, wl, P, solver, greeks=True)
@@ -242,11 +245,17 @@ def test_fused_greeks_match_separate_call_and_oracle(fv, solver):
     st, sg = host(st), host(sig)
     ok = st == 0
     assert ok.mean() > 0.999
+    i = np.where(ok)[0]
+    _, theta_terms = greek_terms("bsm", wl.fs[i], wl.K[i], wl.T[i], wl.r[i], wl.q[i], sg[i],
+                                 wl.flag[i], P[i])
     for name in gk:
         a = host(gk[name])
         assert np.all(np.isnan(a[~ok])), name
-        assert np.array_equal(a[ok], host(g2[name])[ok]), name
-    i = np.where(ok)[0]
+        b = host(g2[name])
+        if name == "theta":
+            assert np.all(np.abs(a[i] - b[i]) <= 4 * U * theta_terms), name
+        else:
+            assert np.array_equal(a[ok], b[ok]), name
     bad, worst = greeks_bad("bsm", wl.fs[i], wl.K[i], wl.T[i], wl.r[i], wl.q[i], sg[i],
                             wl.flag[i], {k: host(v)[i] for k, v in gk.items()})
     print("fused-greeks/%s: max err/tol %.3g" % (solver, worst))
