@@ -214,24 +214,35 @@ typedef struct {
     double lr, beta1, beta2, eps;        /* Adam hyper-parameters */
 } fv_svi_problem;
 
-/* One Adam step of the calibration, as two launches on `stream` that
- * allocate nothing and never synchronise (capturable in a hipGraph):
- * per-maturity gradients (one workgroup per maturity; SVI -> Black-76 price
- * -> LBR implied volatility -> implicit-function adjoint, reduced in a fixed
- * order, so results are bitwise reproducible), then the Adam update with the
- * loss.  The price reaches the solver as the normalised price b(x, s) of its
- * out-of-the-money side, the value the solver's own reduction of the
- * discounted price recovers.
+/* Size in doubles of the workspace fv_svi_adam_step needs for problem p:
+ * 2 + 8 n_maturities + ceil(n_maturities / 4)
+ *   + 6 (ceil(n_quotes / 64) + n_maturities).
+ * Negative (an FV_E_* code) when p is invalid. */
+int64_t fv_svi_workspace_size(const fv_svi_problem *p);
+
+/* One Adam step of the calibration, as four launches on `stream` that
+ * allocate nothing and never synchronise (capturable in a hipGraph): the
+ * per-maturity natural parameters; the per-quote chain SVI -> Black-76
+ * price -> LBR implied volatility -> implicit-function adjoint, one wave per
+ * 64 consecutive quotes, summed per (wave, maturity) run; per maturity the
+ * sums of its runs in a fixed order, the gradient and the Adam update; the
+ * loss, a fixed-order sum (not launched when loss is NULL or loss_len is
+ * 0).  No atomics: results are bitwise reproducible.  The price reaches the
+ * solver as the normalised price b(x, s) of its out-of-the-money side, the
+ * value the solver's own reduction of the discounted price recovers.
  *   theta, adam_m, adam_v: [5 n_maturities] in/out (moments start at 0);
  *   step: one device int64 (Adam's step count t, read then incremented);
- *   grad: [5 n_maturities] out, scratch: gradient at the pre-update theta;
- *   loss_parts: [n_maturities] out, scratch;
+ *   grad: [5 n_maturities] out: gradient at the pre-update theta;
+ *   workspace: device scratch of workspace_len >= fv_svi_workspace_size(p)
+ *   doubles (FV_E_INVALID_ARG if smaller); the step writes every value it
+ *   reads there before reading it, so its contents between calls do not
+ *   matter; steps that share a workspace must not overlap in time;
  *   loss: [loss_len] history (may be NULL): loss[t] receives the loss at the
  *   pre-update theta of step t (t read from *step; nothing written when
  *   t >= loss_len).  A replayed graph thus records every step's loss. */
 int fv_svi_adam_step(const fv_svi_problem *p, double *theta, double *adam_m, double *adam_v,
-                     int64_t *step, double *grad, double *loss_parts, double *loss,
-                     int64_t loss_len, void *stream);
+                     int64_t *step, double *grad, double *workspace, int64_t workspace_len,
+                     double *loss, int64_t loss_len, void *stream);
 
 /* sigma_SVI of every quote at parameters theta [5 n_maturities];
  * sigma_out [n_quotes] (NaN where w <= 0). */

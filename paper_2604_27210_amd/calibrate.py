@@ -1,8 +1,8 @@
 """SVI calibration through the differentiable implied volatility, one Adam
 step per replay of a captured hipGraph (torch.cuda.CUDAGraph is hipGraph on
-ROCm).  All arithmetic is in ``fv_svi_adam_step`` (two kernel launches,
+ROCm).  All arithmetic is in ``fv_svi_adam_step`` (three kernel launches,
 no allocation, no host synchronisation); this module only owns the device
-buffers, the capture and the replays.
+buffers (state and workspace), the capture and the replays.
 """
 from __future__ import annotations
 
@@ -51,15 +51,18 @@ class SviCalibrator:
         self.v = torch.zeros_like(self.theta)
         self.step_count = torch.zeros(1, dtype=torch.int64, device=dev)
         self.grad = torch.empty_like(self.theta)
-        self.loss_parts = torch.empty(self.n_mat, dtype=torch.float64, device=dev)
+        nws = N.load().fv_svi_workspace_size(ctypes.byref(self.problem))
+        if nws < 0:
+            N.check(int(nws), "fv_svi_workspace_size")
+        self.workspace = torch.empty(int(nws), dtype=torch.float64, device=dev)
         self.loss = torch.full((max_steps,), float("nan"), dtype=torch.float64, device=dev)
         self.graph = None
 
     def step(self):
         N.check(N.load().fv_svi_adam_step(
             ctypes.byref(self.problem), api._ptr(self.theta), api._ptr(self.m), api._ptr(self.v),
-            api._ptr(self.step_count), api._ptr(self.grad), api._ptr(self.loss_parts),
-            api._ptr(self.loss), self.loss.numel(), ctypes.c_void_p(api._stream_ptr())),
+            api._ptr(self.step_count), api._ptr(self.grad), api._ptr(self.workspace),
+            self.workspace.numel(), api._ptr(self.loss), self.loss.numel(), ctypes.c_void_p(api._stream_ptr())),
             "fv_svi_adam_step")
 
     def capture(self):

@@ -24,6 +24,7 @@
 #include "../../include/fastvol.h"
 #include "fv_f32.h"
 #include "fv_host.h"
+#include "fv_csr.h"
 #include "fv_quote.h"
 
 // Error state shared by every entry point of the library (fv_host.h).
@@ -472,63 +473,6 @@ struct KChains {
   const int8_t* flag;
 };
 
-// ---- wave-cooperative CSR location (all 64 lanes of a wave take part, the
-// results are wave-uniform).
-constexpr int64_t kOffEnd = INT64_MAX;
-
-__device__ __forceinline__ int64_t ld_off(const int64_t* __restrict__ off, int64_t count,
-                                          int64_t idx) {
-  return idx < count ? off[idx] : kOffEnd;
-}
-
-__device__ __forceinline__ int64_t readlane64(int64_t v, int lane) {
-  const uint64_t u = (uint64_t)v;
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-// Largest m in [0, count) with off[m] <= key (off non-decreasing, off[0] <=
-// key): a 64-ary search, each level one load per lane at 64 evenly spaced
-// candidates and a ballot, so log64(count) dependent loads instead of
-// log2(count).  The loads stay below `hi` <= count; malformed (decreasing)
-// offsets still shrink [lo, hi) every level.
-__device__ __forceinline__ int64_t wave_locate(const int64_t* __restrict__ off, int64_t count,
-                                               int64_t key) {
-  const int64_t lane = __lane_id();
-  int64_t lo = 0, hi = count;
-  while (hi - lo > 1) {
-    const int64_t step = (hi - lo + 63) >> 6;
-    const int64_t idx = lo + (lane + 1) * step;
-    const bool le = idx < hi && off[idx] <= key;
-    const int cnt = __popcll(__ballot(le));
-    lo += (int64_t)cnt * step;
-    hi = min(hi, lo + step);
-  }
-  return lo;
-}
-
-// The next 64 starts after `base` (lane j holds off[base + 1 + j], or kOffEnd
-// past the last entry), consumed in order through a wave-uniform cursor.
-struct OffWindow {
-  const int64_t* off;
-  int64_t count, base, v;
-  int j;
-  __device__ __forceinline__ void init(const int64_t* o, int64_t c, int64_t b) {
-    off = o; count = c; base = b; j = 0;
-    v = ld_off(off, count, base + 1 + __lane_id());
-  }
-  __device__ __forceinline__ int64_t peek() {
-    if (j == 64) {
-      base += 64;
-      j = 0;
-      v = ld_off(off, count, base + 1 + __lane_id());
-    }
-    return readlane64(v, j);
-  }
-  __device__ __forceinline__ void pop() { ++j; }
-};
-
 // Ragged-chain kernel: one launch over the CSR offsets.  Chunks of
 // blockDim*qpt consecutive quotes go to workgroups (a chunk loop strides by
 // the grid, one chunk per workgroup at the launch sizes used); inside a chunk every
@@ -550,27 +494,14 @@ __attribute__((amdgpu_waves_per_eu(FV_CHAINS_WAVES_PER_EU))) void k_iv_chains(
   for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
     const int64_t w0 = ch * chunk + wave_in_block * wave_span;  // wave's first quote
     if (w0 >= c.n) continue;
-    int64_t mstart = wave_locate(c.mat_quote_off, c.n_mat, w0);
-    int64_t cstart = wave_locate(c.chain_mat_off, c.n_chains, mstart);
-    OffWindow mw, cw;
-    mw.init(c.mat_quote_off, c.n_mat, mstart);
-    cw.init(c.chain_mat_off, c.n_chains, cstart);
+    fv::ChainCursor cur;
+    cur.init(c.mat_quote_off, c.n_mat, c.chain_mat_off, c.n_chains, w0);
     for (int k = 0; k < qpt; ++k) {
       const int64_t i0 = w0 + (int64_t)k * 64;
       if (i0 >= c.n) break;
       const int64_t i = i0 + lane;
-      const int64_t ilast = min(i0 + 63, c.n - 1);
-      // maturity of every lane: starts at or before i0, then those inside
-      while (mw.peek() <= i0) { ++mstart; mw.pop(); }
-      int64_t m = mstart, npop = 0;
-      for (int64_t b; (b = mw.peek()) <= ilast; mw.pop(), ++npop) m += (i >= b);
-      // chain of every lane, keyed by maturity
-      const int64_t mlast = mstart + npop;
-      while (cw.peek() <= mstart) { ++cstart; cw.pop(); }
-      int64_t cc = cstart, cpop = 0;
-      for (int64_t b; (b = cw.peek()) <= mlast; cw.pop(), ++cpop) cc += (m >= b);
-      mstart += npop;
-      cstart += cpop;
+      int64_t m, cc;
+      cur.slice(i0, min(i0 + 63, c.n - 1), i, m, cc);
       if (i >= c.n) continue;
       const double F = c.F[cc], r = c.r[cc], T = c.T[m];
       const double P = c.price[i], K = c.K[i];

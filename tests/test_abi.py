@@ -174,3 +174,21 @@ def test_bench_refuses_more_than_one_gpu():
                          capture_output=True, text=True, timeout=300)
     assert res.returncode != 0
     assert "measures one GPU" in res.stdout + res.stderr
+
+
+def test_svi_workspace_size_and_small_workspace(lib):
+    """fv_svi_workspace_size follows the documented layout, and a step with
+    a smaller workspace is refused before anything is launched (the arrays
+    below are never dereferenced)."""
+    from paper_2604_27210_amd import _native as N
+    assert lib.fv_svi_workspace_size(None) == N.FV_E_INVALID_ARG
+    fake = 0x1000
+    for n_mat, n in ((1, 1), (7, 64), (7, 65), (7529, 2080919)):
+        ch = N.FvChains(1, n_mat, n, fake, fake, fake, fake, fake, None, fake, fake)
+        prob = N.FvSviProblem(ch, fake, 1e-2, 0.9, 0.999, 1e-8)
+        need = lib.fv_svi_workspace_size(ctypes.byref(prob))
+        assert need == 2 + 8 * n_mat + (n_mat + 3) // 4 + 6 * ((n + 63) // 64 + n_mat)
+        v = ctypes.c_void_p(fake)
+        rc = lib.fv_svi_adam_step(ctypes.byref(prob), v, v, v, v, v, v, need - 1, None, 0, None)
+        assert rc == N.FV_E_INVALID_ARG
+        assert b"workspace" in lib.fv_last_error()
