@@ -244,6 +244,23 @@ int fv_svi_adam_step(const fv_svi_problem *p, double *theta, double *adam_m, dou
                      int64_t *step, double *grad, double *workspace, int64_t workspace_len,
                      double *loss, int64_t loss_len, void *stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * step as fv_svi_adam_step, with its workspace taken from an array the
+ * library holds on each GPU (8 MiB, 1,048,576 doubles, kept until the
+ * process ends) instead of a caller buffer.  Problems whose
+ * fv_svi_workspace_size exceeds that get FV_E_INVALID_ARG and launch
+ * nothing.  Nothing is allocated: the array is part of the loaded code
+ * object, and its address is looked up once per device (on the first call
+ * with that device current).  Every call on one GPU shares that GPU's
+ * array, so calls that overlap in time on one GPU (two streams, two host
+ * threads) race and must be serialised by the caller.  The step writes
+ * every workspace value it reads before reading it, so what an earlier call
+ * left there does not matter. */
+int fv_svi_adam_step_noalloc(const fv_svi_problem *p, double *theta, double *adam_m,
+                             double *adam_v, int64_t *step, double *grad, double *loss,
+                             int64_t loss_len, void *stream);
+
 /* sigma_SVI of every quote at parameters theta [5 n_maturities];
  * sigma_out [n_quotes] (NaN where w <= 0). */
 int fv_svi_vols(const fv_svi_problem *p, const double *theta, double *sigma_out, void *stream);

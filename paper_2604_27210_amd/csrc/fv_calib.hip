@@ -35,6 +35,10 @@
 
 #include <stdint.h>
 
+#include <atomic>
+#include <mutex>
+#include <string>
+
 #include "../../include/fastvol.h"
 #include "fv_csr.h"
 #include "fv_host.h"
@@ -429,6 +433,45 @@ int launch_step(const fv_svi_problem* p, double* theta, double* adam_m, double* 
   return fvh::launched("fv_svi_adam_step");
 }
 
+// Workspace of the allocation-free step: one array per GPU, part of the
+// library's code object (each device that loads the library holds its own
+// copy until the process ends).  Host code never passes `scratch` itself to
+// a kernel (on the host the name is only a stand-in): it takes the device
+// address from hipGetSymbolAddress, once per device, with that device
+// current.
+constexpr int64_t kScratchDoubles = (int64_t)1 << 20;  // 8 MiB
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+std::mutex g_scratch_mu;
+std::atomic<double*> g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's `scratch` into *out; FV_OK or an
+// FV_E_* code with its text set.
+int scratch_of_current_device(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fvh::fail(FV_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fvh::fail(FV_E_UNSUPPORTED, "device ordinal beyond the 64 the library tracks");
+  double* ptr = g_scratch_ptr[dev].load(std::memory_order_acquire);
+  if (!ptr) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    ptr = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+    if (!ptr) {
+      void* p = nullptr;
+      e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p)
+        return fvh::fail(FV_E_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                       (e != hipSuccess ? hipGetErrorString(e) : "NULL address"));
+      ptr = static_cast<double*>(p);
+      g_scratch_ptr[dev].store(ptr, std::memory_order_release);
+    }
+  }
+  *out = ptr;
+  return FV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -448,6 +491,23 @@ int fv_svi_adam_step(const fv_svi_problem* p, double* theta, double* adam_m, dou
   if (workspace_len < workspace_doubles(p->chains.n_maturities, p->chains.n_quotes))
     return fvh::fail(FV_E_INVALID_ARG, "workspace smaller than fv_svi_workspace_size()");
   return launch_step(p, theta, adam_m, adam_v, step, grad, workspace, loss, loss_len, stream);
+}
+
+int fv_svi_adam_step_noalloc(const fv_svi_problem* p, double* theta, double* adam_m,
+                             double* adam_v, int64_t* step, double* grad, double* loss,
+                             int64_t loss_len, void* stream) {
+  int rc = check_problem(p);
+  if (rc) return rc;
+  const int64_t need = workspace_doubles(p->chains.n_maturities, p->chains.n_quotes);
+  if (need > kScratchDoubles)
+    return fvh::fail(FV_E_INVALID_ARG,
+                     "problem needs " + std::to_string(need) +
+                         " doubles of workspace; the allocation-free step holds at most " +
+                         std::to_string(kScratchDoubles) + " (8 MiB): use fv_svi_adam_step");
+  double* ws = nullptr;
+  rc = scratch_of_current_device(&ws);
+  if (rc) return rc;
+  return launch_step(p, theta, adam_m, adam_v, step, grad, ws, loss, loss_len, stream);
 }
 
 int fv_svi_vols(const fv_svi_problem* p, const double* theta, double* sigma_out, void* stream) {
