@@ -73,6 +73,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--settle-ms", type=float, default=200.0,
+                    help="before the warmup steps, repeat the step untimed for this long: "
+                         "after an idle spell the GPU raises its clock over the first ~40 ms "
+                         "of sustained load (about 100 launches of this kernel run 5-20%% "
+                         "slower), and the timed steps are to measure the sustained rate; "
+                         "0 disables it (the line then reports the post-idle rate)")
     ap.add_argument("--n", type=int, default=10_000_000, help="quotes per step")
     ap.add_argument("--solver", default="lbr", choices=["lbr", "halley"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -90,6 +96,10 @@ def parse():
                     help="instead of the bench: throughput of LBR and Halley IV, pricing and "
                          "Greeks on the first N quotes of the wide workload, N = 1e3 .. 1e8 "
                          "(one JSON line per N)")
+    ap.add_argument("--clock-series", action="store_true",
+                    help="instead of the bench: after 2 s of idle, 40 blocks of 50 back-to-back "
+                         "LBR launches with a 2 s pause after block 20; per block the mean, "
+                         "first, min and max launch time (how the clock ramps under load)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="instead of the bench: copy a 1 GiB device buffer three times "
                          "(the reference launch that scales FETCH_SIZE / WRITE_SIZE to bytes)")
@@ -169,7 +179,20 @@ def cpu_baseline(wl, P, sample, reps=3):
             "host": {"cpu_model": _cpu_model(), "nproc": os.cpu_count()}}
 
 
-def _time(torch, fn, reps=10, warm=2):
+def _settle(torch, fn, ms=100.0):
+    """Repeat fn untimed for `ms` of wall time, so that the timing after it
+    sees the GPU's sustained clock rather than its ramp after host-side
+    setup (see --settle-ms)."""
+    t0 = time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < ms:
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+
+
+def _time(torch, fn, reps=10, warm=2, settle_ms=100.0):
+    if settle_ms > 0:
+        _settle(torch, fn, settle_ms)
     for _ in range(warm):
         fn()
     torch.cuda.synchronize()
@@ -320,6 +343,8 @@ def extras(fv, torch, main_inputs):
     args = (d(chc.chain_mat_off, torch.int64), d(chc.mat_quote_off, torch.int64), d(chc.F),
             d(chc.r), d(chc.T), cK, cfl, iv_t)
     res = {}
+    # 200 untimed steps of a throw-away calibrator first (sustained clock)
+    calibrate_svi(SviCalibrator(*args, raw_from_natural(cal.theta0)), 200, graph=False)
     for graph in (False, True):
         c = SviCalibrator(*args, raw_from_natural(cal.theta0))
         r_ = calibrate_svi(c, 200, graph=graph)
@@ -339,6 +364,29 @@ def extras(fv, torch, main_inputs):
     out["svi_calibration_500_chains"] = dict(n_quotes=chc.n, n_maturities=chc.n_mat,
                                              steps=200, **res)
     return out
+
+
+def clock_series(fv, torch, P, S, K, T, r, q, flag):
+    """Launch times of the LBR kernel in blocks of 50 back-to-back launches,
+    from an idle GPU, with a 2 s pause after block 20."""
+    call = lambda: fv.implied_vol("bsm", P, S, K, T, r, flag=flag, q=q)
+    torch.cuda.synchronize()
+    time.sleep(2.0)
+    t0 = time.perf_counter()
+    for blk in range(40):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(50)]
+        for e0, e1 in evs:
+            e0.record()
+            call()
+            e1.record()
+        torch.cuda.synchronize()
+        ms = [e0.elapsed_time(e1) for e0, e1 in evs]
+        print(json.dumps({"block": blk, "t_s": round(time.perf_counter() - t0, 3),
+                          "mean_ms": round(float(np.mean(ms)), 4), "first_ms": round(ms[0], 4),
+                          "min_ms": round(min(ms), 4), "max_ms": round(max(ms), 4)}), flush=True)
+        if blk == 19:
+            time.sleep(2.0)
 
 
 def n_sweep(fv, torch):
@@ -419,6 +467,9 @@ def main():
     if a.census:
         census(fv, torch, P, S, K, T, r, q, flag)
         return
+    if a.clock_series:
+        clock_series(fv, torch, P, S, K, T, r, q, flag)
+        return
     if a.copy_probe:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -432,6 +483,27 @@ def main():
     def step():
         return fv.implied_vol("bsm", P, S, K, T, r, flag=flag, q=q, solver=a.solver)
 
+    # the same rate right after an idle spell (no settling), for the record
+    post_idle = None
+    if a.settle_ms > 0 and not a.no_extras:
+        torch.cuda.synchronize()
+        time.sleep(1.0)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(a.warmup + a.steps)]
+        for e0, e1 in evs:
+            e0.record(stream)
+            step()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        post_idle = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs[a.warmup:]]))
+    settle = {"ms": 0.0, "launches": 0}
+    t_settle = time.perf_counter()
+    while (time.perf_counter() - t_settle) * 1e3 < a.settle_ms:
+        for _ in range(10):
+            step()
+        settle["launches"] += 10
+        torch.cuda.synchronize()
+    settle["ms"] = (time.perf_counter() - t_settle) * 1e3
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
@@ -485,6 +557,11 @@ def main():
         "warmup": a.warmup,
         "ms_per_step": ms,
         "kernel_ms_mean": float(np.mean(kern_ms)),
+        "clock_settle": {"ms": settle["ms"], "launches": settle["launches"],
+                         "kernel_ms_mean_post_idle": post_idle,
+                         "note": "untimed steps before the warmup, until the GPU holds its "
+                                 "sustained clock; kernel_ms_mean_post_idle is the timed "
+                                 "window's mean when it starts after 1 s of idle"},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -74,11 +74,11 @@ struct GreekOut {
 // Largest workgroup the kernels are compiled for (8 waves).
 constexpr int kMaxBlock = 512;
 // Minimum resident waves per SIMD the solver kernels are register-allocated
-// for (2: up to 256 VGPRs, 3: 168, 4: 128).  The plain solver kernels fit 4
-// without spilling; their fused-Greeks variants keep more live values and
-// are held at 2 so that they do not spill.
+// for (2: up to 256 VGPRs, 3: 168, 4: 128, 6: 80).  The plain solver kernels
+// fit 6 without spilling (8 spills to scratch); their fused-Greeks variants
+// keep more live values and are held at 2 so that they do not spill.
 #ifndef FV_SOLVER_WAVES_PER_EU
-#define FV_SOLVER_WAVES_PER_EU 4
+#define FV_SOLVER_WAVES_PER_EU 6
 #endif
 #define FV_WAVES(GREEKS) ((GREEKS) ? 2 : FV_SOLVER_WAVES_PER_EU)
 // The ragged kernel keeps its CSR windows live across the solve; held to the
@@ -134,7 +134,7 @@ __attribute__((amdgpu_waves_per_eu(FV_WAVES(GREEKS)))) void k_iv_lbr(KQuotes q, 
     double sg = st == fv::kQAtIntrinsic ? 0.0 : __builtin_nan("");
     if (st == fv::kQOk) {
       const LbrResult res = fv::lbr_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kLbrMinSteps, kLbrMaxSteps, kLbrStepTol);
-      sg = res.s / rd.sqrtT;
+      sg = res.s * rd.isqrtT;
       if (!res.converged) st = fv::kQNotConverged;
     }
     sig_out[i] = sg;
@@ -217,7 +217,7 @@ __attribute__((amdgpu_waves_per_eu(FV_WAVES(GREEKS)))) void k_iv_halley(KQuotes 
       double sg = st == fv::kQAtIntrinsic ? 0.0 : __builtin_nan("");
       if (st == fv::kQOk) {
         hs = fv::halley_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kHalleySteps);
-        sg = hs.s / rd.sqrtT;
+        sg = hs.s * rd.isqrtT;
         fail = !hs.converged;
       }
       if (!fail) {
@@ -267,7 +267,7 @@ __attribute__((amdgpu_waves_per_eu(FV_WAVES(GREEKS)))) void k_iv_halley(KQuotes 
     const Reduced rd = fv::reduce_quote(MODEL, P, fs, K, T, r, qy, th);
     const double s =
         fv::bisection_solve(rd.x, rd.beta, rd.bmax, rd.lnb, queue[j].lo, queue[j].hi, kBisectTol);
-    const double sg = s / rd.sqrtT;
+    const double sg = s * rd.isqrtT;
     sig_out[i] = sg;
     if (st_out) st_out[i] = fv::kQOk;
     if (GREEKS) {
@@ -513,14 +513,14 @@ __attribute__((amdgpu_waves_per_eu(FV_CHAINS_WAVES_PER_EU))) void k_iv_chains(
         if (SOLVER == FV_SOLVER_LBR) {
           const LbrResult res =
               fv::lbr_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kLbrMinSteps, kLbrMaxSteps, kLbrStepTol);
-          sg = res.s / rd.sqrtT;
+          sg = res.s * rd.isqrtT;
           if (!res.converged) st = fv::kQNotConverged;
         } else {
           fv::HalleyState hs = fv::halley_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kHalleySteps);
           double s = hs.s;
           if (!hs.converged)
             s = fv::bisection_solve(rd.x, rd.beta, rd.bmax, rd.lnb, hs.lo, hs.hi, kBisectTol);
-          sg = s / rd.sqrtT;
+          sg = s * rd.isqrtT;
         }
       }
       sig_out[i] = sg;

@@ -101,7 +101,7 @@ template <bool LO>
 __host__ __device__ inline double householder3_step_t(int obj, double x, double s, double beta,
                                                        double inv_ln_beta, double ln_bmax_m_beta,
                                                        const NBlack& nb) {
-  const double is = rcp_lo(s);
+  const double is = nb.is;
   const double x2is2 = x * x * is * is;
   const double eta = x2is2 * is - 0.25 * s;                       // b''/b'
   const double eta3b = eta * eta - 3.0 * x2is2 * is * is - 0.25;  // b'''/b'
@@ -257,14 +257,19 @@ __host__ __device__ __attribute__((always_inline)) inline double lbr_initial_gue
   // The lower-map cubic leaves (0, 0) with slope 1, so for a beta below the
   // normal range f = beta (1 + O(beta)): then ln p = (ln beta - ln cl)/3 is
   // taken from ln beta, which stays finite where f and p underflow.
+  // R1: p = (f/cl)^{1/3} as exp(ln(f/cl)/3), ln(f/cl) from ln beta where
+  // the cubic's value is below the normal range; R4: p = f.  One logarithm
+  // either way.
   const double f = fmax(y, 1e-300);
-  double p = r1 ? fmin(cbrt(f * rcp_lo(cl)), 0.4999999999) : fmin(f, 0.5);
-  double lnp;
-  if (r1 && y < 0x1p-960) {
-    lnp = (ln_beta - flog_lo(cl)) * (1.0 / 3.0);
-    p = 0.0;
+  const bool deep = r1 && y < 0x1p-960;
+  const double la = flog_lo(r1 ? (deep ? cl : f * rcp_lo(cl)) : fmin(f, 0.5));
+  double p, lnp;
+  if (r1) {
+    lnp = fmin((deep ? ln_beta - la : la) * (1.0 / 3.0), -0.69314718076);  // p <= 0.4999999999
+    p = deep ? 0.0 : fexp_lo(lnp);
   } else {
-    lnp = flog_lo(p);
+    lnp = la;
+    p = fmin(f, 0.5);
   }
   const double zi = inv_norm_cdf_lower_ln(p, lnp);
   return r1 ? -ax * (1.0 / kSqrt3) * rcp_lo(zi) : -2.0 * zi;
@@ -354,7 +359,7 @@ __host__ __device__ __attribute__((always_inline)) inline double halley_step(
     double x, double beta, double bmax, double ln_beta, bool logres, double s, HalleyState& st,
     double& res) {
   const NBlack nb = normalised_black(x, s, bmax);
-  const double is0 = rcp_lo(s);
+  const double is0 = nb.is;
   const double eta = x * x * is0 * is0 * is0 - 0.25 * s;  // b''/b'
   double sn;
   if (logres) {

@@ -330,6 +330,7 @@ struct NBlack {
   double cratio; // (b_max - b) / b' in the complement form, free of the
                  // common factor E (b_max - b and b' underflow together)
   double lnbp;   // ln b' = -(h^2 + t^2)/2 - ln sqrt(2 pi)
+  double is;     // 1/s (at the evaluation's precision), for the caller's step
   int form;      // evaluation form taken (kFormDifference or kFormComplement)
 };
 
@@ -352,10 +353,12 @@ __host__ __device__ inline NBlack normalised_black_t(double x, double s, double 
     r.ratio = atm ? s : 0.0;
     r.cratio = __builtin_inf();
     r.lnbp = atm ? -kLnSqrt2Pi : -__builtin_inf();
+    r.is = rcp_lo(s);
     r.form = kFormDifference;
     return r;
   }
-  const double h = x * (LO ? rcp_lo(s) : rcp(s)), t = 0.5 * s;
+  r.is = LO ? rcp_lo(s) : rcp(s);
+  const double h = x * r.is, t = 0.5 * s;
   const double ea = -0.5 * fma(h, h, t * t);
   const double E = LO ? fexp_lo(ea) : fexp(ea);
   r.bp = kInvSqrt2Pi * E;

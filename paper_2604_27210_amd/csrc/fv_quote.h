@@ -30,7 +30,8 @@ enum QuoteStatus : uint8_t {
 };
 
 struct Reduced {
-  double F, D, sqrtT;
+  double F, D;
+  double isqrtT;   // 1/sqrt(T): sigma = s isqrtT
   double x, beta;  // normalised out-of-the-money call: x <= 0, 0 < beta < e^{x/2}
   double bmax;     // e^{x/2} = min(F, K)/sqrt(F K)
   double lnb;      // ln beta, to full relative precision also where beta is below
@@ -50,6 +51,13 @@ __host__ __device__ inline double sqrt_pos(double T) {
   const bool tiny = T < 1e-290;
   const double Ts = tiny ? T * 0x1p+200 : T;
   return Ts * rsqrt(Ts) * (tiny ? 0x1p-100 : 1.0);
+}
+
+// 1/sqrt(T) for finite T > 0, with the same scaling of tiny T
+__host__ __device__ inline double rsqrt_pos(double T) {
+  const bool tiny = T < 1e-290;
+  const double Ts = tiny ? T * 0x1p+200 : T;
+  return rsqrt(Ts) * (tiny ? 0x1p+100 : 1.0);
 }
 
 // e^{a b} with the rounding error of the exponent carried into the result:
@@ -94,7 +102,7 @@ __host__ __device__ inline double log_moneyness(double F, double K) {
 __host__ __device__ inline Reduced reduce_quote(int model, double price, double fs, double K,
                                                 double T, double r, double q, int theta) {
   Reduced o;
-  o.F = 0.0; o.D = 0.0; o.sqrtT = 0.0; o.x = 0.0; o.beta = 0.0; o.bmax = 0.0; o.lnb = 0.0;
+  o.F = 0.0; o.D = 0.0; o.isqrtT = 0.0; o.x = 0.0; o.beta = 0.0; o.bmax = 0.0; o.lnb = 0.0;
   // S/F and K must be normal numbers (the refined hardware reciprocals
   // below need normal operands); so must the forward
   const bool ok_in = finite_d(price) && finite_d(fs) && finite_d(K) && finite_d(T) &&
@@ -109,7 +117,7 @@ __host__ __device__ inline Reduced reduce_quote(int model, double price, double 
   const double M = theta > 0 ? F : K;
   o.F = F;
   o.D = D;
-  o.sqrtT = sqrt_pos(T);
+  o.isqrtT = rsqrt_pos(T);
   if (Pu < I) { o.status = kQBelowIntrinsic; return o; }
   if (Pu == I) { o.status = kQAtIntrinsic; return o; }
   if (Pu >= M) { o.status = kQAboveMax; return o; }
@@ -118,6 +126,8 @@ __host__ __device__ inline Reduced reduce_quote(int model, double price, double 
   o.x = th > 0 ? lx : -lx;
   // 1/sqrt(F K) as two factors: F K itself leaves the binary64 range once F
   // and K are beyond about 1e+-154, while the normalised quantities do not
+  // (and scaling price, F and K by an even power of two scales both factors
+  // exactly, so the result is bitwise homogeneous of degree 0)
   const double isq = rsqrt(F) * rsqrt(K);
   o.beta = (Pu - I) * isq;
   o.bmax = fmin(F, K) * isq;

@@ -36,13 +36,13 @@ void h_iv_b76(int solver, int64_t n, const double* P, const double* F, const dou
     if (s_ == fv::kQOk) {
       if (solver == 0) {
         const fv::LbrResult res = fv::lbr_solve(rd.x, rd.beta, rd.bmax, rd.lnb, 2, 4, 1e-6);
-        sg = res.s / rd.sqrtT;
+        sg = res.s * rd.isqrtT;
         if (!res.converged) s_ = fv::kQNotConverged;
       } else {
         const fv::HalleyState hs = fv::halley_solve(rd.x, rd.beta, rd.bmax, rd.lnb, 8);
         double s = hs.s;
         if (!hs.converged) s = fv::bisection_solve(rd.x, rd.beta, rd.bmax, rd.lnb, hs.lo, hs.hi, 1e-13);
-        sg = s / rd.sqrtT;
+        sg = s * rd.isqrtT;
       }
     }
     sig[i] = sg;
