@@ -281,6 +281,15 @@ def extras(fv, torch, main_inputs):
     ms_p = _time(torch, persistent)
     ms_pc = _time_cold(torch, persistent)
     ms_f = _time(torch, lambda: fv.implied_vol("black76", Pc, fF, Kq, fT, fr, flag=flq))
+    # what a caller without the ragged call pays: gather the per-chain F, r
+    # and per-maturity T to per-quote arrays on the device, then the flat call
+    mat_q = d(ch.mat_of_quote(), torch.int64)
+    chain_q = d(ch.chain_of_mat()[ch.mat_of_quote()], torch.int64)
+
+    def expand_then_flat():
+        eF, eT, er = F.index_select(0, chain_q), Tm.index_select(0, mat_q), rc.index_select(0, chain_q)
+        return fv.implied_vol("black76", Pc, eF, Kq, eT, er, flag=flq)
+    ms_ef = _time(torch, expand_then_flat)
     off = ch.mat_quote_off[ch.chain_mat_off]
 
     def per_chain():
@@ -292,6 +301,7 @@ def extras(fv, torch, main_inputs):
     out["ragged_b76_chains"] = {"n_quotes": ch.n, "n_chains": ch.n_chains, "n_maturities": ch.n_mat,
                                 "persistent_ms": ms_p, "persistent_cold_ms": ms_pc,
                                 "flat_expanded_ms": ms_f,
+                                "expand_on_device_then_flat_ms": ms_ef,
                                 "per_chain_launches_ms": ms_c,
                                 "persistent_implied_vols_per_s": ch.n / ms_p * 1e3}
     # forward + backward (differentiable IV), 1M quotes

@@ -473,36 +473,44 @@ struct KChains {
   const int8_t* flag;
 };
 
-// Ragged-chain kernel: one launch over the CSR offsets.  Chunks of
-// blockDim*qpt consecutive quotes go to workgroups (a chunk loop strides by
-// the grid, one chunk per workgroup at the launch sizes used); inside a chunk every
-// wave owns 64*qpt consecutive quotes and takes them 64 at a time (each step
-// one coalesced 512-byte load per field).  The wave finds the maturity and
-// chain of its first quote by two 64-ary searches, then keeps a window of the
-// next 64 maturity starts and chain starts in registers: each 64-quote slice
-// reads the starts that fall inside it (a few wave-uniform readlanes, usually
-// none) and every lane gets its maturity and chain without a search of its own.
+// Ragged-chain kernel: one launch over the CSR offsets, one wave per 64
+// consecutive quotes (one coalesced 512-byte load per field).  The wave
+// finds the maturity and chain of its first quote by two 64-ary searches
+// and every lane its own from the next 64 maturity and chain starts; each
+// wave locates afresh, so no cursor state is live across the solve.  The
+// Halley path compacts the lanes that fail its convergence check into an
+// LDS queue (wave ballots, as the flat Halley kernel does) and the
+// workgroup bisects the packed queue afterwards.
+struct ChainPending {
+  int64_t i;
+  int32_t m, cc;  // maturity and chain of quote i
+  double lo, hi;
+};
+
 template <int SOLVER>
 __global__ __launch_bounds__(kMaxBlock)
 __attribute__((amdgpu_waves_per_eu(FV_CHAINS_WAVES_PER_EU))) void k_iv_chains(
-    KChains c, double* __restrict__ sig_out, uint8_t* __restrict__ st_out, int qpt) {
-  const int64_t chunk = (int64_t)blockDim.x * qpt;
-  const int64_t n_chunks = (c.n + chunk - 1) / chunk;
-  const int64_t wave_span = 64 * (int64_t)qpt;
-  const int64_t wave_in_block = threadIdx.x >> 6;
-  const int64_t lane = __lane_id();
-  for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
-    const int64_t w0 = ch * chunk + wave_in_block * wave_span;  // wave's first quote
-    if (w0 >= c.n) continue;
+    KChains c, double* __restrict__ sig_out, uint8_t* __restrict__ st_out) {
+  constexpr bool kHalley = SOLVER == FV_SOLVER_HALLEY;
+  extern __shared__ unsigned char smem_raw[];
+  ChainPending* queue = reinterpret_cast<ChainPending*>(smem_raw);
+  __shared__ int qcount;
+  if (kHalley) {
+    if (threadIdx.x == 0) qcount = 0;
+    __syncthreads();
+  }
+  const int64_t i0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64;
+  const int64_t i = i0 + __lane_id();
+  bool fail = false;
+  fv::HalleyState hs;
+  hs.lo = 0.0;
+  hs.hi = 0.0;
+  int64_t m = 0, cc = 0;
+  if (i0 < c.n) {  // wave-uniform: every lane of the wave takes part in the search
     fv::ChainCursor cur;
-    cur.init(c.mat_quote_off, c.n_mat, c.chain_mat_off, c.n_chains, w0);
-    for (int k = 0; k < qpt; ++k) {
-      const int64_t i0 = w0 + (int64_t)k * 64;
-      if (i0 >= c.n) break;
-      const int64_t i = i0 + lane;
-      int64_t m, cc;
-      cur.slice(i0, min(i0 + 63, c.n - 1), i, m, cc);
-      if (i >= c.n) continue;
+    cur.init(c.mat_quote_off, c.n_mat, c.chain_mat_off, c.n_chains, i0);
+    cur.slice(i0, min(i0 + 63, c.n - 1), i, m, cc);
+    if (i < c.n) {
       const double F = c.F[cc], r = c.r[cc], T = c.T[m];
       const double P = c.price[i], K = c.K[i];
       const int th = c.flag[i];
@@ -510,22 +518,53 @@ __attribute__((amdgpu_waves_per_eu(FV_CHAINS_WAVES_PER_EU))) void k_iv_chains(
       uint8_t st = rd.status;
       double sg = st == fv::kQAtIntrinsic ? 0.0 : __builtin_nan("");
       if (st == fv::kQOk) {
-        if (SOLVER == FV_SOLVER_LBR) {
-          const LbrResult res =
-              fv::lbr_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kLbrMinSteps, kLbrMaxSteps, kLbrStepTol);
+        if (!kHalley) {
+          const LbrResult res = fv::lbr_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kLbrMinSteps,
+                                              kLbrMaxSteps, kLbrStepTol);
           sg = res.s * rd.isqrtT;
           if (!res.converged) st = fv::kQNotConverged;
         } else {
-          fv::HalleyState hs = fv::halley_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kHalleySteps);
-          double s = hs.s;
-          if (!hs.converged)
-            s = fv::bisection_solve(rd.x, rd.beta, rd.bmax, rd.lnb, hs.lo, hs.hi, kBisectTol);
-          sg = s * rd.isqrtT;
+          hs = fv::halley_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kHalleySteps);
+          sg = hs.s * rd.isqrtT;
+          fail = !hs.converged;
         }
       }
-      sig_out[i] = sg;
-      if (st_out) st_out[i] = st;
+      if (!fail) {
+        sig_out[i] = sg;
+        if (st_out) st_out[i] = st;
+      }
     }
+  }
+  if (!kHalley) return;
+  // wave-level compaction of the failing lanes into the LDS queue
+  const uint64_t mask = __ballot(fail);
+  if (mask) {
+    int wbase = 0;
+    const int cnt = __popcll(mask);
+    const unsigned first = __ffsll((unsigned long long)mask) - 1;
+    if (__lane_id() == first) wbase = atomicAdd(&qcount, cnt);
+    wbase = __shfl(wbase, first);
+    if (fail) {
+      const int slot = wbase + __popcll(mask & lanemask_lt());
+      queue[slot].i = i;
+      queue[slot].m = (int32_t)m;
+      queue[slot].cc = (int32_t)cc;
+      queue[slot].lo = hs.lo;
+      queue[slot].hi = hs.hi;
+    }
+  }
+  __syncthreads();
+  // bisection fallback over the packed queue: every lane of a wave works
+  const int nq = qcount;
+  for (int j = threadIdx.x; j < nq; j += blockDim.x) {
+    const int64_t iq = queue[j].i;
+    const int64_t mq = queue[j].m, cq = queue[j].cc;
+    const Reduced rd = fv::reduce_quote(fv::kBlack76, c.price[iq], c.F[cq], c.K[iq], c.T[mq],
+                                        c.r[cq], 0.0, c.flag[iq]);
+    const double s =
+        fv::bisection_solve(rd.x, rd.beta, rd.bmax, rd.lnb, queue[j].lo, queue[j].hi, kBisectTol);
+    sig_out[iq] = s * rd.isqrtT;
+    if (st_out) st_out[iq] = fv::kQOk;
   }
 }
 
@@ -656,6 +695,7 @@ constexpr size_t kMaxQueueBytes = 65536;
 size_t queue_bytes(int kernel, int block, int qpt) {
   if (kernel == FV_KERNEL_IV_HALLEY) return sizeof(Pending) * (size_t)block * qpt;
   if (kernel == FV_KERNEL_IV_HALLEY_F32) return sizeof(Pending32) * (size_t)block * qpt;
+  if (kernel == FV_KERNEL_CHAINS) return sizeof(ChainPending) * (size_t)block;  // Halley path
   return 0;
 }
 
@@ -1045,6 +1085,9 @@ int fv_implied_vol_chains(int solver, const fv_chains* c, double* sigma_out,
   if (c->n_chains < 0 || c->n_maturities < 0 || c->n_quotes < 0)
     return fail(FV_E_INVALID_ARG, "negative size");
   if (c->n_quotes == 0) return FV_OK;
+  if (c->n_quotes > kMaxQuotes) return fail(FV_E_INVALID_ARG, "n_quotes above 2^31 - 1 workgroups of 64");
+  if (c->n_maturities > 0x7fffffff || c->n_chains > 0x7fffffff)
+    return fail(FV_E_INVALID_ARG, "more than 2^31 - 1 maturities or chains");
   if (c->n_chains == 0 || c->n_maturities == 0)
     return fail(FV_E_INVALID_ARG, "quotes without chains or maturities");
   if (!c->chain_mat_off || !c->mat_quote_off || !c->F || !c->r || !c->T || !c->price ||
@@ -1063,19 +1106,16 @@ int fv_implied_vol_chains(int solver, const fv_chains* c, double* sigma_out,
   k.K = c->K;
   k.flag = c->flag;
   const LaunchShape sh = shape_for(FV_KERNEL_CHAINS, FV_MODEL_BLACK76, k.n);
-  const int64_t chunk = (int64_t)sh.block * sh.qpt;
-  const int64_t n_chunks = (k.n + chunk - 1) / chunk;
-  // One workgroup per chunk: the hardware hands chunks to CUs as waves
-  // retire, which balances the per-quote cost spread (wave divergence,
-  // bisection tails) better than a resident grid dealing chunks statically
-  // (measured on the ragged Black-76 workload: 0.35 ms vs 0.39-0.44 ms).
-  // The kernel's chunk loop keeps any grid valid beyond the 2^31-1 limit.
-  const dim3 grid((unsigned)std::min<int64_t>(n_chunks, 0x7fffffff)), block(sh.block);
+  // one wave per 64 consecutive quotes, blockDim/64 waves per workgroup; the
+  // quote count is capped (kMaxQuotes) so that the grid fits
+  const int64_t n_blocks = (k.n + sh.block - 1) / sh.block;
+  const dim3 grid((unsigned)n_blocks), block(sh.block);
   hipStream_t s = (hipStream_t)stream;
   if (solver == FV_SOLVER_LBR)
-    k_iv_chains<FV_SOLVER_LBR><<<grid, block, 0, s>>>(k, sigma_out, status_out, sh.qpt);
+    k_iv_chains<FV_SOLVER_LBR><<<grid, block, 0, s>>>(k, sigma_out, status_out);
   else
-    k_iv_chains<FV_SOLVER_HALLEY><<<grid, block, 0, s>>>(k, sigma_out, status_out, sh.qpt);
+    k_iv_chains<FV_SOLVER_HALLEY><<<grid, block, sizeof(ChainPending) * (size_t)sh.block, s>>>(
+        k, sigma_out, status_out);
   return launched("fv_implied_vol_chains");
 }
 
