@@ -56,11 +56,18 @@ struct KQuotes {
   int8_t flag_value;
 };
 
+// A field's value for quote i: its array entry, or its broadcast value.
+// ARR = true is the specialisation for calls whose per-quote fields are all
+// arrays (checked on the host): the pointer-or-value choice per field and
+// its condition, which the solver kernels otherwise keep across the whole
+// solve, disappear.
+template <bool ARR = false>
 __device__ __forceinline__ double ld(const fv_arg& a, int64_t i) {
-  return a.ptr ? a.ptr[i] : a.value;
+  return ARR ? a.ptr[i] : (a.ptr ? a.ptr[i] : a.value);
 }
+template <bool ARR = false>
 __device__ __forceinline__ int ldflag(const KQuotes& q, int64_t i) {
-  return q.flag ? (int)q.flag[i] : (int)q.flag_value;
+  return ARR ? (int)q.flag[i] : (q.flag ? (int)q.flag[i] : (int)q.flag_value);
 }
 
 struct GreekOut {
@@ -117,7 +124,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_price(KQuotes q, fv_arg sigma, do
 }
 
 // ------------------------------------------------------------- IV: LBR
-template <int MODEL, bool GREEKS>
+template <int MODEL, bool GREEKS, bool ARR>
 __global__ __launch_bounds__(kMaxBlock)
 __attribute__((amdgpu_waves_per_eu(FV_WAVES(GREEKS)))) void k_iv_lbr(KQuotes q, double* __restrict__ sig_out, uint8_t* __restrict__ st_out,
                          GreekOut g, int qpt) {
@@ -125,10 +132,10 @@ __attribute__((amdgpu_waves_per_eu(FV_WAVES(GREEKS)))) void k_iv_lbr(KQuotes q, 
   for (int k = 0; k < qpt; ++k) {
     const int64_t i = base + (int64_t)k * blockDim.x;
     if (i >= q.n) return;
-    const double P = ld(q.price, i), fs = ld(q.fs, i), K = ld(q.K, i), T = ld(q.T, i),
-                 r = ld(q.r, i);
-    const double qy = MODEL == fv::kBlackScholesMerton ? ld(q.q, i) : 0.0;
-    const int th = ldflag(q, i);
+    const double P = ld<ARR>(q.price, i), fs = ld<ARR>(q.fs, i), K = ld<ARR>(q.K, i), T = ld<ARR>(q.T, i),
+                 r = ld<ARR>(q.r, i);
+    const double qy = MODEL == fv::kBlackScholesMerton ? ld<ARR>(q.q, i) : 0.0;
+    const int th = ldflag<ARR>(q, i);
     const Reduced rd = fv::reduce_quote(MODEL, P, fs, K, T, r, qy, th);
     uint8_t st = rd.status;
     double sg = st == fv::kQAtIntrinsic ? 0.0 : __builtin_nan("");
@@ -190,7 +197,7 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
 
-template <int MODEL, bool GREEKS>
+template <int MODEL, bool GREEKS, bool ARR>
 __global__ __launch_bounds__(kMaxBlock)
 __attribute__((amdgpu_waves_per_eu(FV_WAVES(GREEKS)))) void k_iv_halley(KQuotes q, double* __restrict__ sig_out,
                             uint8_t* __restrict__ st_out, GreekOut g, int qpt) {
@@ -208,10 +215,10 @@ __attribute__((amdgpu_waves_per_eu(FV_WAVES(GREEKS)))) void k_iv_halley(KQuotes 
     hs.lo = 0.0;
     hs.hi = 0.0;
     if (i < q.n) {
-      const double P = ld(q.price, i), fs = ld(q.fs, i), K = ld(q.K, i), T = ld(q.T, i),
-                   r = ld(q.r, i);
-      const double qy = MODEL == fv::kBlackScholesMerton ? ld(q.q, i) : 0.0;
-      const int th = ldflag(q, i);
+      const double P = ld<ARR>(q.price, i), fs = ld<ARR>(q.fs, i), K = ld<ARR>(q.K, i), T = ld<ARR>(q.T, i),
+                   r = ld<ARR>(q.r, i);
+      const double qy = MODEL == fv::kBlackScholesMerton ? ld<ARR>(q.q, i) : 0.0;
+      const int th = ldflag<ARR>(q, i);
       const Reduced rd = fv::reduce_quote(MODEL, P, fs, K, T, r, qy, th);
       uint8_t st = rd.status;
       double sg = st == fv::kQAtIntrinsic ? 0.0 : __builtin_nan("");
@@ -260,10 +267,10 @@ __attribute__((amdgpu_waves_per_eu(FV_WAVES(GREEKS)))) void k_iv_halley(KQuotes 
   const int m = qcount;
   for (int j = threadIdx.x; j < m; j += blockDim.x) {
     const int64_t i = queue[j].i;
-    const double P = ld(q.price, i), fs = ld(q.fs, i), K = ld(q.K, i), T = ld(q.T, i),
-                 r = ld(q.r, i);
-    const double qy = MODEL == fv::kBlackScholesMerton ? ld(q.q, i) : 0.0;
-    const int th = ldflag(q, i);
+    const double P = ld<ARR>(q.price, i), fs = ld<ARR>(q.fs, i), K = ld<ARR>(q.K, i), T = ld<ARR>(q.T, i),
+                 r = ld<ARR>(q.r, i);
+    const double qy = MODEL == fv::kBlackScholesMerton ? ld<ARR>(q.q, i) : 0.0;
+    const int th = ldflag<ARR>(q, i);
     const Reduced rd = fv::reduce_quote(MODEL, P, fs, K, T, r, qy, th);
     const double s =
         fv::bisection_solve(rd.x, rd.beta, rd.bmax, rd.lnb, queue[j].lo, queue[j].hi, kBisectTol);
@@ -933,10 +940,15 @@ int fv_implied_vol(int model, int solver, const fv_quotes* q, double* sigma_out,
   }
   const KQuotes k = to_k(q);
   hipStream_t s = (hipStream_t)stream;
+  // every per-quote field an array (q only matters for Black-Scholes-Merton)
+  const bool arr = q->price.ptr && q->fs.ptr && q->K.ptr && q->T.ptr && q->r.ptr && q->flag &&
+                   (model != FV_MODEL_BSM || q->q.ptr);
   if (solver == FV_SOLVER_LBR) {
     const LaunchShape sh = shape_for(FV_KERNEL_IV_LBR, model, q->n);
     const dim3 grid = grid_for(q->n, sh), block(sh.block);
-#define FV_LBR(M, G) k_iv_lbr<M, G><<<grid, block, 0, s>>>(k, sigma_out, status_out, g, sh.qpt)
+#define FV_LBR(M, G)                                                                   \
+  (arr ? k_iv_lbr<M, G, true><<<grid, block, 0, s>>>(k, sigma_out, status_out, g, sh.qpt) \
+       : k_iv_lbr<M, G, false><<<grid, block, 0, s>>>(k, sigma_out, status_out, g, sh.qpt))
     switch (model * 2 + (g.any ? 1 : 0)) {
       case 0: FV_LBR(0, false); break;
       case 1: FV_LBR(0, true); break;
@@ -951,7 +963,9 @@ int fv_implied_vol(int model, int solver, const fv_quotes* q, double* sigma_out,
   const LaunchShape sh = shape_for(FV_KERNEL_IV_HALLEY, model, q->n);
   const dim3 grid = grid_for(q->n, sh), block(sh.block);
   const size_t lds = sizeof(Pending) * (size_t)sh.block * sh.qpt;
-#define FV_HAL(M, G) k_iv_halley<M, G><<<grid, block, lds, s>>>(k, sigma_out, status_out, g, sh.qpt)
+#define FV_HAL(M, G)                                                                    \
+  (arr ? k_iv_halley<M, G, true><<<grid, block, lds, s>>>(k, sigma_out, status_out, g, sh.qpt) \
+       : k_iv_halley<M, G, false><<<grid, block, lds, s>>>(k, sigma_out, status_out, g, sh.qpt))
   switch (model * 2 + (g.any ? 1 : 0)) {
     case 0: FV_HAL(0, false); break;
     case 1: FV_HAL(0, true); break;
