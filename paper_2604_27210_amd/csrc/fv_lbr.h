@@ -176,7 +176,7 @@ __host__ __device__ __attribute__((always_inline)) inline double lbr_initial_gue
   // terms cancel exactly in s_l (truncation after a^7: < a^6/24 relative).
   const double sax = sqrt_lo(ax);
   const double sc = kSqrt2 * sax;
-  double om = 1.0 - erfcx_lo(sax);        // 1 - erfcx(a)
+  double om = 1.0 - erfcx_g(sax);         // 1 - erfcx(a)
   double sl = sc - kSqrtPiOver2 * om;     // s_l
   if (sax < 0.03) {
     constexpr double c3 = 4.0 / (3.0 * kSqrtPi), c5 = 8.0 / (15.0 * kSqrtPi),
@@ -196,7 +196,7 @@ __host__ __device__ __attribute__((always_inline)) inline double lbr_initial_gue
   // the other boundary point on the side of beta
   const double ibc = rcp_lo_safe(nc.bp);  // b' may underflow to 0
   const double so = lower_half ? fmax(sl, 0.0) : sc + nc.c * ibc;
-  const NBlack no = normalised_black_t<true>(x, so, bmax);
+  const NBlack no = normalised_black_t<2>(x, so, bmax);
   const double ibo = rcp_lo_safe(no.bp);
 
   const bool r1 = lower_half && beta < no.b;
@@ -226,8 +226,8 @@ __host__ __device__ __attribute__((always_inline)) inline double lbr_initial_gue
     const double iso = rcp_lo(so);
     const double eta_o = x * x * iso * iso * iso - 0.25 * so;  // b''/b' at s_o
     const double z = r1 ? -ax * (1.0 / kSqrt3) * iso : -0.5 * so;
-    const double ez = fexp_lo(-0.5 * z * z);
-    const double Pz = 0.5 * ez * erfcx_lo(-z * kInvSqrt2);  // Phi(z), z <= 0
+    const double ez = fexp_g(-0.5 * z * z);
+    const double Pz = 0.5 * ez * erfcx_g(-z * kInvSqrt2);   // Phi(z), z <= 0
     const double pz = kInvSqrt2Pi * ez;                          // phi(z)
     double f0, f1, f2;  // f, df/ds, d2f/ds2 at s_o
     if (r1) {
@@ -266,12 +266,12 @@ __host__ __device__ __attribute__((always_inline)) inline double lbr_initial_gue
   double p, lnp;
   if (r1) {
     lnp = fmin((deep ? ln_beta - la : la) * (1.0 / 3.0), -0.69314718076);  // p <= 0.4999999999
-    p = deep ? 0.0 : fexp_lo(lnp);
+    p = deep ? 0.0 : fexp_g(lnp);
   } else {
     lnp = la;
     p = fmin(f, 0.5);
   }
-  const double zi = inv_norm_cdf_lower_ln(p, lnp);
+  const double zi = inv_norm_cdf_lower_ln_g(p, lnp);
   return r1 ? -ax * (1.0 / kSqrt3) * rcp_lo(zi) : -2.0 * zi;
 }
 
@@ -298,7 +298,7 @@ __host__ __device__ __attribute__((always_inline)) inline LbrResult lbr_solve(
   int it = 0;
   double ds = 0.0;
   if (max_steps > 0) {
-    const NBlack nb = normalised_black_t<true>(x, s, bmax);
+    const NBlack nb = normalised_black_t<1>(x, s, bmax);
     if (trace) *trace |= (uint32_t)nb.form << 8;
     ds = householder3_step_t<true>(obj, x, s, beta, inv_ln_beta, ln_bmax_m_beta, nb);
     s += ds;

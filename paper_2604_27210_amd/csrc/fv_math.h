@@ -207,6 +207,22 @@ __host__ __device__ inline double fexp_lo(double x) {
   return ldexp(p, (int)n);
 }
 
+// e^x with the reduction of fexp and the Taylor series to degree 6
+// (truncation < 1.3e-7 on |r| <= ln2/2), for the initial guess only
+__host__ __device__ inline double fexp_g(double x) {
+  x = x < -1000.0 ? -1000.0 : x;
+  const double n = rint(x * kLog2E);
+  const double r = fma(-n, kLn2Lo, fma(-n, kLn2Hi, x));
+  double p = 1.0 / 720.0;
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)n);
+}
+
 // ln x with the reduction of flog and five terms of the atanh series
 // (truncation < 7e-10 for |f| <= 0.1716)
 __host__ __device__ inline double flog_lo(double x) {
@@ -243,15 +259,19 @@ __host__ __device__ inline double erfcx_fit(double z) {
   return p * R;
 }
 
-// The same form with the guess-precision fit (relative error ~1e-8).
+// Degree of the first Householder step's fit (relative error ~1e-8).
 constexpr int kErfcxLoDeg = (int)(sizeof(coef::kErfcxLo) / sizeof(double)) - 1;
 
-__host__ __device__ inline double erfcx_lo(double z) {
-  const double R = rcp_lo(z + coef::kErfcxLoB);
-  const double y = (z - (coef::kErfcxLoB - 2.0 * coef::kErfcxZ0)) * R;
-  double p = coef::kErfcxLo[kErfcxLoDeg];
+// The same form with the initial guess's fit (degree 7, relative error
+// ~4e-6): the guess lands a few percent from the root, far above that.
+constexpr int kErfcxGDeg = (int)(sizeof(coef::kErfcxG) / sizeof(double)) - 1;
+
+__host__ __device__ inline double erfcx_g(double z) {
+  const double R = rcp_lo(z + coef::kErfcxGB);
+  const double y = (z - (coef::kErfcxGB - 2.0 * coef::kErfcxZ0)) * R;
+  double p = coef::kErfcxG[kErfcxGDeg];
 #pragma unroll
-  for (int i = kErfcxLoDeg - 1; i >= 0; --i) p = fma(p, y, coef::kErfcxLo[i]);
+  for (int i = kErfcxGDeg - 1; i >= 0; --i) p = fma(p, y, coef::kErfcxG[i]);
   return p * R;
 }
 
@@ -267,30 +287,20 @@ __host__ __device__ inline double norm_cdf(double z) {
 }
 
 // Inverse standard normal CDF for p in (0, 1/2] (returns a value <= 0), as
-// (p - 1/2) P(r)/Q(r) with r = sqrt(-2 ln p): one branch on the whole range,
-// relative error ~5e-8 (fitted, fv_coeffs.h).  Only initial guesses use it.
-constexpr int kPhiInvDegP = (int)(sizeof(coef::kPhiInvP) / sizeof(double)) - 1;
-constexpr int kPhiInvDegQ = (int)(sizeof(coef::kPhiInvQ) / sizeof(double)) - 1;
-
-// p in (0, 1/2] with its logarithm lnp (which stays finite when p
+// (p - 1/2) P(r)/Q(r) with r = sqrt(-2 ln p): one [5/5] rational on the
+// whole range, relative error ~7e-5 (fitted, fv_coeffs.h).  Only the
+// initial guess uses it, with p's logarithm lnp (which stays finite when p
 // underflows: then p - 1/2 is -1/2).
-__host__ __device__ inline double inv_norm_cdf_lower_ln(double p, double lnp) {
-  const double r = sqrt_lo(-2.0 * lnp);
-  double num = coef::kPhiInvP[kPhiInvDegP], den = coef::kPhiInvQ[kPhiInvDegQ];
-#pragma unroll
-  for (int i = kPhiInvDegP - 1; i >= 0; --i) num = fma(num, r, coef::kPhiInvP[i]);
-#pragma unroll
-  for (int i = kPhiInvDegQ - 1; i >= 0; --i) den = fma(den, r, coef::kPhiInvQ[i]);
-  return (p - 0.5) * fdiv_lo(num, den);
-}
+constexpr int kPhiInvGDegP = (int)(sizeof(coef::kPhiInvGP) / sizeof(double)) - 1;
+constexpr int kPhiInvGDegQ = (int)(sizeof(coef::kPhiInvGQ) / sizeof(double)) - 1;
 
-__host__ __device__ inline double inv_norm_cdf_lower(double p) {
-  const double r = sqrt_lo(-2.0 * flog_lo(p));
-  double num = coef::kPhiInvP[kPhiInvDegP], den = coef::kPhiInvQ[kPhiInvDegQ];
+__host__ __device__ inline double inv_norm_cdf_lower_ln_g(double p, double lnp) {
+  const double r = sqrt_lo(-2.0 * lnp);
+  double num = coef::kPhiInvGP[kPhiInvGDegP], den = coef::kPhiInvGQ[kPhiInvGDegQ];
 #pragma unroll
-  for (int i = kPhiInvDegP - 1; i >= 0; --i) num = fma(num, r, coef::kPhiInvP[i]);
+  for (int i = kPhiInvGDegP - 1; i >= 0; --i) num = fma(num, r, coef::kPhiInvGP[i]);
 #pragma unroll
-  for (int i = kPhiInvDegQ - 1; i >= 0; --i) den = fma(den, r, coef::kPhiInvQ[i]);
+  for (int i = kPhiInvGDegQ - 1; i >= 0; --i) den = fma(den, r, coef::kPhiInvGQ[i]);
   return (p - 0.5) * fdiv_lo(num, den);
 }
 
@@ -336,11 +346,14 @@ struct NBlack {
 
 enum NbForm : int { kFormDifference = 0, kFormComplement = 1 };
 
-// x <= 0, s >= 0, bmax = exp(x/2).  LO = true evaluates at guess precision
-// (erfcx fit of degree 12, shorter exp, one-step reciprocals: ~1e-8
-// relative in b and in b_max - b), for the boundary points of the guess.
-template <bool LO>
+// x <= 0, s >= 0, bmax = exp(x/2).  Precision level P: 0 full binary64;
+// 1 (the first Householder step) erfcx fit of degree 12, shorter exp,
+// one-step reciprocals, ~1e-8 relative in b and in b_max - b; 2 (the
+// boundary point of the initial guess) erfcx fit of degree 7 and a
+// degree-6 exp, ~1e-5.
+template <int P>
 __host__ __device__ inline NBlack normalised_black_t(double x, double s, double bmax) {
+  constexpr bool LO = P >= 1;
   NBlack r;
   if (!(s > 0x1p-1000)) {
     // s = 0, or so small that x/s would overflow: the limit s -> 0, where b
@@ -360,15 +373,15 @@ __host__ __device__ inline NBlack normalised_black_t(double x, double s, double 
   r.is = LO ? rcp_lo(s) : rcp(s);
   const double h = x * r.is, t = 0.5 * s;
   const double ea = -0.5 * fma(h, h, t * t);
-  const double E = LO ? fexp_lo(ea) : fexp(ea);
+  const double E = P == 0 ? fexp(ea) : (P == 1 ? fexp_lo(ea) : fexp_g(ea));
   r.bp = kInvSqrt2Pi * E;
   r.lnbp = ea - kLnSqrt2Pi;
   const double q1 = -(h + t) * kInvSqrt2, q2 = (t - h) * kInvSqrt2;
   const bool comp = q1 < -coef::kErfcxZ0;
   const double z1 = comp ? -q1 : q1;
-  constexpr int kDeg = LO ? kErfcxLoDeg : kErfcxDeg;
-  constexpr const double* kC = LO ? coef::kErfcxLo : coef::kErfcx;
-  constexpr double kB = LO ? coef::kErfcxLoB : coef::kErfcxB;
+  constexpr int kDeg = P == 0 ? kErfcxDeg : (P == 1 ? kErfcxLoDeg : kErfcxGDeg);
+  constexpr const double* kC = P == 0 ? coef::kErfcx : (P == 1 ? coef::kErfcxLo : coef::kErfcxG);
+  constexpr double kB = P == 0 ? coef::kErfcxB : (P == 1 ? coef::kErfcxLoB : coef::kErfcxGB);
   constexpr double kShift = kB - 2.0 * coef::kErfcxZ0;
   const double R1 = LO ? rcp_lo(z1 + kB) : rcp(z1 + kB);
   const double R2 = LO ? rcp_lo(q2 + kB) : rcp(q2 + kB);
@@ -402,7 +415,7 @@ __host__ __device__ inline NBlack normalised_black_t(double x, double s, double 
 }
 
 __host__ __device__ inline NBlack normalised_black(double x, double s, double bmax) {
-  return normalised_black_t<false>(x, s, bmax);
+  return normalised_black_t<0>(x, s, bmax);
 }
 
 // b''/b' and b'''/b' as functions of s (closed forms of the derivatives of

@@ -21,19 +21,22 @@ definitions evaluated in mpmath (no coefficients are taken from any library):
    evaluator uses divided differences of p.
 
    A second, lower-degree fit of the same form (``kErfcxLo``, relative error
-   ~1e-8) serves the initial guess of the implied-volatility iteration,
-   which only has to land within ~1e-3 of the root for two quartically
-   convergent steps to reach binary64 precision.  A third
+   ~1e-8) serves the first Householder step of the implied-volatility
+   iteration, and a third (``kErfcxG``, degree 7, ~4e-6) the boundary
+   points and wing maps of its initial guess, which only has to land within
+   a few percent of the root for two quartically convergent steps to reach
+   binary64 precision.  A third
    (``kErfcxF32``, degree 13, value ~6e-10 and derivative ~2.4e-7 relative)
    serves the binary32 solver, where binary32 rounding dominates both.
 
 2. The inverse standard normal CDF on (0, 1/2] (initial guess only), as one
-   rational function in the tail variable r = sqrt(-2 ln p) of the ratio
-   G(r) = Phi^{-1}(p)/(p - 1/2): G -> sqrt(2 pi) at p = 1/2 and grows like
-   2r in the tail, smooth on the whole range, so one branch covers
+   [5/5] rational function in the tail variable r = sqrt(-2 ln p) of the
+   ratio G(r) = Phi^{-1}(p)/(p - 1/2): G -> sqrt(2 pi) at p = 1/2 and grows
+   like 2r in the tail, smooth on the whole range, so one branch covers
    p in [1e-310, 1/2] without the central/tail split of Wichura's AS 241
    (Appl. Stat. 37, 1988).  Fitted by iteratively re-weighted linearised
-   least squares (relative error ~5e-8, ample for a starting point).
+   least squares (relative error ~7e-5, ample for a starting point that
+   lands a few percent from the root).
 """
 from __future__ import annotations
 
@@ -48,7 +51,9 @@ ERFCX_LO_B = mp.mpf("3.5")
 ERFCX_LO_DEG = 12
 ERFCX_F32_B = mp.mpf("3.5")
 ERFCX_F32_DEG = 13
-PHI_INV_DEG = (9, 9)
+ERFCX_G_B = mp.mpf("3.0")
+ERFCX_G_DEG = 7
+PHI_INV_G_DEG = (5, 5)
 P_MIN = mp.mpf("1e-310")
 
 
@@ -135,7 +140,7 @@ def fit_rational(ts, fs, m, n, iters=4):
     return P, Q, err
 
 
-def fit_phi_inv(N=140):
+def fit_phi_inv(N=80, deg=PHI_INV_G_DEG):
     half = mp.mpf("0.5")
     ra = mp.sqrt(-2 * mp.log(half))
     rb = mp.sqrt(-2 * mp.log(P_MIN))
@@ -144,7 +149,7 @@ def fit_phi_inv(N=140):
     for r in rs:
         p = mp.exp(-r * r / 2)
         fs.append(ndtri(p) / (p - half))
-    P, Q, _ = fit_rational(rs, fs, *PHI_INV_DEG, iters=6)
+    P, Q, _ = fit_rational(rs, fs, *deg, iters=6)
     # relative error of Phi^{-1} itself on a dense grid (coefficients rounded)
     Pd = [mp.mpf(float(v)) for v in P]
     Qd = [mp.mpf(float(v)) for v in Q]
@@ -170,18 +175,22 @@ def main():
     lo_err, lo_deriv = check_erfcx(el, ERFCX_LO_B)
     e32 = fit_erfcx(ERFCX_F32_B, ERFCX_F32_DEG)
     f32_err, f32_deriv = check_erfcx(e32, ERFCX_F32_B)
-    pP, pQ, perr = fit_phi_inv()
+    eg = fit_erfcx(ERFCX_G_B, ERFCX_G_DEG)
+    g_err, g_deriv = check_erfcx(eg, ERFCX_G_B)
+    gP, gQ, gerr = fit_phi_inv()
     n3 = lambda v: mp.nstr(v, 3)
     out = [
         "// Generated by gen_coeffs.py -- do not edit by hand.\n",
         "// erfcx(z), z >= -Z0:  erfcx = p(y)/(z + B),  y = (z - B + 2 Z0)/(z + B).\n",
         "// erfcx fit max rel err %s, derivative max rel err %s\n" % (n3(eval_err), n3(deriv_err)),
-        "// guess-precision erfcx (same form, B = kErfcxLoB): max rel err %s, derivative %s\n"
+        "// first-Householder-step erfcx (same form, B = kErfcxLoB): max rel err %s, derivative %s\n"
         % (n3(lo_err), n3(lo_deriv)),
         "// binary32 erfcx (same form, B = kErfcxF32B): max rel err %s, derivative %s\n"
         % (n3(f32_err), n3(f32_deriv)),
+        "// initial-guess erfcx (same form, B = kErfcxGB): max rel err %s, derivative %s\n"
+        % (n3(g_err), n3(g_deriv)),
         "// Inverse normal CDF on (0, 1/2]: Phi^{-1}(p) = (p - 1/2) P(r)/Q(r),\n",
-        "// r = sqrt(-2 ln p); max rel err %s\n" % n3(perr),
+        "// r = sqrt(-2 ln p), [5/5]; max rel err %s\n" % n3(gerr),
         "#pragma once\n\nnamespace fv {\nnamespace coef {\n\n",
         "constexpr double kErfcxZ0 = %s;\n" % mp.nstr(ERFCX_Z0, 20),
         "constexpr double kErfcxB = %s;\n" % mp.nstr(ERFCX_B, 20),
@@ -190,16 +199,18 @@ def main():
         _arr("kErfcxLo", el),
         "\nconstexpr double kErfcxF32B = %s;\n" % mp.nstr(ERFCX_F32_B, 20),
         _arr("kErfcxF32", e32),
+        "\nconstexpr double kErfcxGB = %s;\n" % mp.nstr(ERFCX_G_B, 20),
+        _arr("kErfcxG", eg),
         "\n",
-        _arr("kPhiInvP", pP),
-        _arr("kPhiInvQ", pQ),
+        _arr("kPhiInvGP", gP),
+        _arr("kPhiInvGQ", gQ),
         "\n}  // namespace coef\n}  // namespace fv\n",
     ]
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "fv_coeffs.h")
     with open(path, "w") as f:
         f.write("".join(out))
     print("wrote", path, "erfcx", n3(eval_err), n3(deriv_err), "erfcx lo", n3(lo_err),
-          n3(lo_deriv), "phi^-1", n3(perr))
+          n3(lo_deriv), "erfcx guess", n3(g_err), "phi^-1", n3(gerr))
 
 
 if __name__ == "__main__":
