@@ -37,10 +37,10 @@ if ROOT not in sys.path:
 # The traffic figure is reported only while the kernel sources still hash to
 # ``source_sha256``; the FLOP figure is the algorithmic count of that source.
 LBR_PROFILE = {
-    "source_sha256": "465ea158f41d1fdeeb8138b4c0da029c34d929f81703d1d3799ba0be7e78cab9",
-    "flop_per_quote": 1179.9,
-    "valu_per_quote": 1128.0,
-    "fetch_bytes_per_quote": 49.039,
+    "source_sha256": "9d6a064c8907ef57c9fcb6a73fdba4b5aad9d6c29fb70a5d3f4693ac2447f51a",
+    "flop_per_quote": 1120.2,
+    "valu_per_quote": 1074.3,
+    "fetch_bytes_per_quote": 49.037,
     "write_bytes_per_quote": 9.009,
 }
 FP64_VECTOR_PEAK_TFLOPS = 78.6
@@ -55,7 +55,7 @@ HBM_PEAK_GBS = 8000.0
 # float64 sigma + uint8 status out
 BYTES_PER_QUOTE = 6 * 8 + 1 + 8 + 1
 KERNEL_SOURCES = ("fv_kernels.hip", "fv_math.h", "fv_lbr.h", "fv_quote.h", "fv_coeffs.h",
-                  "fv_host.h")
+                  "fv_host.h", "fv_csr.h", "fv_f32.h")
 
 
 def kernel_source_sha256() -> str:
@@ -88,14 +88,25 @@ def parse():
                     help="skip the secondary measurements (Halley, small batch, ragged chains, "
                          "forward+backward, calibration)")
     ap.add_argument("--census", action="store_true",
-                    help="instead of the bench: group the quotes by LBR path (fv_lbr_trace), "
-                         "then run the LBR kernel once on the workload as generated and once "
-                         "with quotes sorted by path, so that FP64 instruction counters "
-                         "(rocprofv3 --pmc) of the sorted launch give the algorithmic work")
+                    help="instead of the bench: group the quotes by LBR path (fv_lbr_trace) and "
+                         "by Halley step count (fv_halley_trace), then run each solver's "
+                         "kernel on the workload as generated and with the quotes sorted, so "
+                         "that FP64 instruction counters (rocprofv3 --pmc) of the sorted "
+                         "launches give the algorithmic work")
+    ap.add_argument("--census-steady", action="store_true",
+                    help="with --census, for a run without the profiler: time each order over "
+                         "20 launches after the settle phase (--settle-ms), at the sustained "
+                         "clock")
     ap.add_argument("--n-sweep", action="store_true",
                     help="instead of the bench: throughput of LBR and Halley IV, pricing and "
                          "Greeks on the first N quotes of the wide workload, N = 1e3 .. 1e8 "
                          "(one JSON line per N)")
+    ap.add_argument("--kernel-census", action="store_true",
+                    help="instead of the bench: launch every other kernel family on its "
+                         "workload three times (pricing, Greeks, the IV adjoint on the 1M "
+                         "differentiation workload, ragged chains with both solvers, one "
+                         "calibration step of the 500-chain problem, binary32 Halley), for "
+                         "rocprofv3 counter passes")
     ap.add_argument("--clock-series", action="store_true",
                     help="instead of the bench: after 2 s of idle, 40 blocks of 50 back-to-back "
                          "LBR launches with a 2 s pause after block 20; per block the mean, "
@@ -177,6 +188,77 @@ def cpu_baseline(wl, P, sample, reps=3):
             "single_thread_sample": "every 10th quote of that sample (%d), one thread, median of "
                                     "%d runs %.2f s wall" % (n1, reps, dt1),
             "host": {"cpu_model": _cpu_model(), "nproc": os.cpu_count()}}
+
+
+HOST_LBR_SRC = r"""
+#include <cstdint>
+#include <omp.h>
+#include "fv_quote.h"
+#include "fv_lbr.h"
+extern "C" {
+int h_threads(void) { return omp_get_max_threads(); }
+// Black-Scholes-Merton implied volatility by LBR, one quote per loop
+// iteration, as the flat kernel runs it per lane
+void h_iv_lbr_bsm(int64_t n, const double* P, const double* S, const double* K,
+                  const double* T, const double* r, const double* q, const int8_t* flag,
+                  double* sig) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    const fv::Reduced rd = fv::reduce_quote(fv::kBlackScholesMerton, P[i], S[i], K[i], T[i],
+                                            r[i], q[i], flag[i]);
+    double sg = rd.status == fv::kQAtIntrinsic ? 0.0 : __builtin_nan("");
+    if (rd.status == fv::kQOk) {
+      const fv::LbrResult res = fv::lbr_solve(rd.x, rd.beta, rd.bmax, rd.lnb, 2, 4, 1e-6);
+      sg = res.converged ? res.s * rd.isqrtT : __builtin_nan("");
+    }
+    sig[i] = sg;
+  }
+}
+}
+"""
+
+
+def host_fp64_lbr(wl, P, sample, reps=3):
+    """Context beside the oracle: the library's own FP64 LBR (the kernels'
+    headers compiled for the host with g++ -O3 and OpenMP), on `sample`
+    quotes strided over the workload, all OpenMP threads; the wall-clock
+    median of `reps` runs. Timing only: nothing else calls this build."""
+    import ctypes
+    import subprocess
+    import tempfile
+    d = tempfile.mkdtemp(prefix="fv_host_lbr_")
+    src, so = os.path.join(d, "h.cpp"), os.path.join(d, "libh.so")
+    with open(src, "w") as f:
+        f.write(HOST_LBR_SRC)
+    csrc = os.path.join(ROOT, "paper_2604_27210_amd", "csrc")
+    cmd = ["g++", "-O3", "-march=native", "-std=gnu++17", "-fopenmp", "-shared", "-fPIC",
+           "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"),
+           "-I" + csrc, src, "-o", so]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        return {"error": "host build failed: " + res.stderr[-300:]}
+    lib = ctypes.CDLL(so)
+    idx = np.linspace(0, wl.n - 1, sample).astype(np.int64)
+    sub = wl.take(idx)
+    arrs = [np.ascontiguousarray(a, dtype=np.float64)
+            for a in (P[idx], sub.fs, sub.K, sub.T, sub.r, sub.q)]
+    fl = np.ascontiguousarray(sub.flag, dtype=np.int8)
+    sig = np.empty(sample)
+    vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    run = lambda: lib.h_iv_lbr_bsm(ctypes.c_int64(sample), *[vp(a) for a in arrs], vp(fl),
+                                   vp(sig))
+    run()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        run()
+        ts.append(time.perf_counter() - t0)
+    dt = float(np.median(ts))
+    threads = int(lib.h_threads())
+    return {"value": sample / dt, "unit": "implied vols/s", "cores": threads,
+            "kind": "library LBR compiled for the host (g++ -O3 -march=native, OpenMP)",
+            "sample": "%d quotes evenly strided over the %d-quote workload, %d threads, "
+                      "median of %d runs %.3f s wall" % (sample, wl.n, threads, reps, dt)}
 
 
 def _settle(torch, fn, ms=100.0):
@@ -376,6 +458,53 @@ def extras(fv, torch, main_inputs):
     return out
 
 
+def kernel_census(fv, torch, P, S, K, T, r, q, flag, sig_true):
+    """Three launches of each non-headline kernel family on its workload
+    (the counter summaries read the last of each)."""
+    from paper_2604_27210_amd import workloads as W
+    from paper_2604_27210_amd.calibrate import SviCalibrator, raw_from_natural
+    d = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt)
+    calls = {}
+    calls["price_bsm_10M"] = lambda: fv.price("bsm", S, K, T, r, sig_true, flag=flag, q=q)
+    calls["greeks_bsm_10M"] = lambda: fv.greeks("bsm", S, K, T, r, sig_true, flag=flag, q=q)
+    f32 = [x.float() for x in (P, S, K, T, r, q)]
+    calls["halley_f32_bsm_10M"] = lambda: fv.implied_vol_f32("bsm", f32[0], f32[1], f32[2], f32[3],
+                                                            f32[4], flag=flag, q=f32[5])
+    wd = W.bsm_diff()
+    x = [d(v) for v in (wd.fs, wd.K, wd.T, wd.r, wd.q)]
+    fld = d(wd.flag, torch.int8)
+    Pd = fv.price("bsm", x[0], x[1], x[2], x[3], d(wd.sigma_true), flag=fld, q=x[4])
+    sd, _ = fv.implied_vol("bsm", Pd, x[0], x[1], x[2], x[3], flag=fld, q=x[4])
+    w = d(wd.extra["w"])
+    calls["iv_backward_bsm_1M"] = lambda: fv.implied_vol_backward("bsm", Pd, x[0], x[1], x[2],
+                                                                  x[3], sd, w, flag=fld, q=x[4])
+    ch = W.b76_chains()
+    flat = ch.flatten()
+    F, rc, Tm, Kq, flq = d(ch.F), d(ch.r), d(ch.T), d(ch.K), d(ch.flag, torch.int8)
+    Pc = fv.price("black76", d(flat.fs), Kq, d(flat.T), d(flat.r), d(ch.sigma_true), flag=flq)
+    co, mo = d(ch.chain_mat_off, torch.int64), d(ch.mat_quote_off, torch.int64)
+    for solver in ("lbr", "halley"):
+        calls["chains_%s_b76_8.4M" % solver] = (
+            lambda solver=solver: fv.implied_vol_chains(co, mo, F, rc, Tm, Pc, Kq, flq,
+                                                        solver=solver))
+    cal = W.svi_calibration(500, seed=5)
+    chc = cal.chains
+    mat = chc.mat_of_quote()
+    chain = chc.chain_of_mat()[mat]
+    cF, cT, cr, cK, cfl = (d(chc.F[chain]), d(chc.T[mat]), d(chc.r[chain]), d(chc.K),
+                           d(chc.flag, torch.int8))
+    Pt = fv.price("black76", cF, cK, cT, cr, d(np.full(chc.n, 0.3)), flag=cfl)
+    iv_t, _ = fv.implied_vol("black76", Pt, cF, cK, cT, cr, flag=cfl)
+    svi = SviCalibrator(d(chc.chain_mat_off, torch.int64), d(chc.mat_quote_off, torch.int64),
+                        d(chc.F), d(chc.r), d(chc.T), cK, cfl, iv_t, raw_from_natural(cal.theta0))
+    calls["svi_step_500_chains"] = svi.step
+    for name, fn in calls.items():
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        print(json.dumps({"kernel_census": name}), flush=True)
+
+
 def clock_series(fv, torch, P, S, K, T, r, q, flag):
     """Launch times of the LBR kernel in blocks of 50 back-to-back launches,
     from an idle GPU, with a 2 s pause after block 20."""
@@ -431,31 +560,59 @@ def n_sweep(fv, torch):
         print(json.dumps(row), flush=True)
 
 
-def census(fv, torch, P, S, K, T, r, q, flag):
-    code = fv.lbr_trace("bsm", P, S, K, T, r, flag=flag, q=q)
-    order = torch.argsort(code.to(torch.int64))
-    cs = code[order]
-    args = [x.index_select(0, order).contiguous() for x in (P, S, K, T, r, q)]
-    fl = flag.index_select(0, order).contiguous()
-    times = {}
-    for label, ins, f in (("as_generated", (P, S, K, T, r, q), flag), ("sorted_by_path", args, fl)):
-        run = lambda: fv.implied_vol("bsm", ins[0], ins[1], ins[2], ins[3], ins[4], flag=f,
-                                     q=ins[5], solver="lbr")
-        # one warm-up launch each, then the median of five timed launches (a
-        # counter run sees 6 dispatches per order: the census reads the last)
-        times[label] = _time(torch, run, reps=5, warm=1)
-    c = cs.cpu().numpy().astype(np.uint32)
-    solved = c != 0xFFFFFFFF
-    region = np.bincount(c[solved] & 3, minlength=4) / solved.sum()
-    steps = np.bincount((c[solved] >> 2) & 3, minlength=3) / solved.sum()
-    n_paths = len(np.unique(c[solved]))
-    print(json.dumps({"census": True, "n": int(P.numel()), "solved": int(solved.sum()),
-                      "distinct_paths": n_paths,
-                      "region_fraction_R1_R4": region.round(4).tolist(),
-                      "steps_fraction_2_3_4": steps.round(5).tolist(),
-                      "ms_as_generated": times["as_generated"],
-                      "ms_sorted_by_path": times["sorted_by_path"],
-                      "launch_order": ["as_generated", "sorted_by_path"]}), flush=True)
+def census(fv, torch, P, S, K, T, r, q, flag, steady_settle_ms=0.0):
+    """Each solver's kernel on the workload as generated and with the quotes
+    sorted by the work each takes (LBR: path code from fv_lbr_trace; Halley:
+    step count and fallback bit from fv_halley_trace), one warm-up launch
+    then five timed ones per order, no settle phase: a counter run
+    (rocprofv3 --pmc) sees 6 dispatches per order and solver, and the
+    sorted order's last dispatch, in which no wave executes a branch another
+    of its lanes skipped, gives the algorithmic counts.
+
+    With steady_settle_ms > 0 (a run without the profiler) each order is
+    instead timed over 20 launches after that long a settle phase, so the
+    times are taken at the sustained clock."""
+    out = {"census": True, "n": int(P.numel()), "steady_settle_ms": steady_settle_ms}
+    for solver, trace in (("lbr", fv.lbr_trace), ("halley", fv.halley_trace)):
+        code = trace("bsm", P, S, K, T, r, flag=flag, q=q)
+        order = torch.argsort(code.to(torch.int64))
+        cs = code[order]
+        args = [x.index_select(0, order).contiguous() for x in (P, S, K, T, r, q)]
+        fl = flag.index_select(0, order).contiguous()
+        times = {}
+        for label, ins, f in (("as_generated", (P, S, K, T, r, q), flag),
+                              ("sorted_by_path", args, fl)):
+            run = lambda: fv.implied_vol("bsm", ins[0], ins[1], ins[2], ins[3], ins[4], flag=f,
+                                         q=ins[5], solver=solver)
+            if steady_settle_ms > 0:
+                times[label] = _time(torch, run, reps=20, warm=3, settle_ms=steady_settle_ms)
+            else:
+                times[label] = _time(torch, run, reps=5, warm=1, settle_ms=0)
+        c = cs.cpu().numpy().astype(np.uint32)
+        solved = c != 0xFFFFFFFF
+        rec = {"solved": int(solved.sum()), "distinct_paths": int(len(np.unique(c[solved]))),
+               "ms_as_generated": times["as_generated"],
+               "ms_sorted_by_path": times["sorted_by_path"]}
+        if solver == "lbr":
+            rec["region_fraction_R1_R4"] = (np.bincount(c[solved] & 3, minlength=4)
+                                            / solved.sum()).round(4).tolist()
+            rec["steps_fraction_2_3_4"] = (np.bincount((c[solved] >> 2) & 3, minlength=3)
+                                           / solved.sum()).round(5).tolist()
+        else:
+            st = c[solved] & 0xFF
+            rec["halley_steps_mean"] = round(float(st.mean()), 4)
+            rec["halley_steps_hist_1_8"] = np.bincount(st, minlength=9)[1:].tolist()
+            rec["fallback_fraction"] = round(float(((c[solved] >> 8) & 1).mean()), 6)
+            # the largest step count in each wave of the as-generated order
+            # (64 consecutive quotes), which the wave runs to
+            cg = code.cpu().numpy().astype(np.uint32)
+            m = len(cg) // 64 * 64
+            w = np.where(cg[:m] == 0xFFFFFFFF, 0, cg[:m] & 0xFF).reshape(-1, 64).max(1)
+            rec["wave_max_steps_mean"] = round(float(w.mean()), 4)
+        out[solver] = rec
+    out["launch_order"] = ["lbr as_generated", "lbr sorted_by_path", "halley as_generated",
+                           "halley sorted_by_path"]
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -475,10 +632,14 @@ def main():
     wl, P, S, K, T, r, q, flag = make_inputs(a.n, torch, fv)
     stream = torch.cuda.current_stream()
     if a.census:
-        census(fv, torch, P, S, K, T, r, q, flag)
+        census(fv, torch, P, S, K, T, r, q, flag,
+               a.settle_ms if a.census_steady else 0.0)
         return
     if a.clock_series:
         clock_series(fv, torch, P, S, K, T, r, q, flag)
+        return
+    if a.kernel_census:
+        kernel_census(fv, torch, P, S, K, T, r, q, flag, torch.from_numpy(wl.sigma_true).cuda())
         return
     if a.copy_probe:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
@@ -587,6 +748,7 @@ def main():
         out["extras"] = extras(fv, torch, (P, S, K, T, r, q, flag))
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, P.cpu().numpy(), a.cpu_sample)
+        out.setdefault("extras", {})["host_fp64_lbr"] = host_fp64_lbr(wl, P.cpu().numpy(), wl.n)
     print(json.dumps(out), flush=True)
 
 

@@ -282,6 +282,14 @@ int fv_normalised_black(int64_t n, const double *x, const double *s, const int8_
  * group quotes by path, e.g. to measure divergence. */
 int fv_lbr_trace(int model, const fv_quotes *q, uint32_t *path_out, void *stream);
 
+/* Diagnostic: the Halley steps each quote takes as fv_implied_vol(...,
+ * FV_SOLVER_HALLEY, ...) solves it (paper section 2.2, the throughput path).
+ * steps_out: uint32 [n]; bits 0-7 the number of Halley steps (1..8),
+ * bit 8 set when the quote fails the convergence check and goes through
+ * the bisection fallback; 0xFFFFFFFF for quotes whose status is not
+ * FV_Q_OK.  Used to group quotes by work, e.g. to measure divergence. */
+int fv_halley_trace(int model, const fv_quotes *q, uint32_t *steps_out, void *stream);
+
 /* Launch-shape control.  fv_set_launch(kernel, block, quotes_per_thread)
  * overrides the launch shape of one kernel family (FV_KERNEL_*); block must
  * be a multiple of 64 in [64, 512] and quotes_per_thread in [1, 16], and for

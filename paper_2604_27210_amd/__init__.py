@@ -10,7 +10,7 @@ The native library is loaded lazily, on the first call that needs it.
 from . import _native  # noqa: F401
 
 __all__ = ["price", "implied_vol", "implied_vol_f32", "greeks", "implied_vol_backward", "implied_vol_chains",
-           "price_backward", "price_autograd", "lbr_trace",
+           "price_backward", "price_autograd", "lbr_trace", "halley_trace",
            "normalised_black", "set_launch", "get_launch", "autotune", "version",
            "autotune_all", "launch_shape", "save_tuning", "load_tuning", "reset_tuning",
            "IVFunction", "implied_vol_autograd"]
@@ -20,7 +20,7 @@ def __getattr__(name):
     if name in ("price", "implied_vol", "implied_vol_f32", "greeks", "implied_vol_backward", "implied_vol_chains",
                 "normalised_black", "set_launch", "get_launch", "autotune", "version",
                 "autotune_all", "launch_shape", "save_tuning", "load_tuning", "reset_tuning",
-                "price_backward", "lbr_trace"):
+                "price_backward", "lbr_trace", "halley_trace"):
         from . import api
         return getattr(api, name)
     if name in ("IVFunction", "implied_vol_autograd", "PriceFunction", "price_autograd"):

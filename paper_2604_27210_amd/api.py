@@ -317,6 +317,16 @@ def lbr_trace(model, price, fs, K, T, r, flag="c", q=None, stream=None) -> torch
     return out
 
 
+def halley_trace(model, price, fs, K, T, r, flag="c", q=None, stream=None) -> torch.Tensor:
+    """Per-quote Halley step count and fallback bit (see fv_halley_trace)."""
+    b = _Batch(price=price, fs=fs, K=K, T=T, r=r, q=q, flag=flag)
+    qs = b.quotes(price, fs, K, T, r, q, flag)
+    out = torch.empty(b.n, dtype=torch.int32, device=b.device)
+    N.check(N.load().fv_halley_trace(_model(model), ctypes.byref(qs), _ptr(out),
+                                     b.stream(stream)), "fv_halley_trace")
+    return out
+
+
 def set_launch(kernel, block: int, quotes_per_thread: int) -> None:
     k = N.KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     N.check(N.load().fv_set_launch(k, int(block), int(quotes_per_thread)), "fv_set_launch")

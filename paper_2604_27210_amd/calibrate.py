@@ -1,6 +1,6 @@
 """SVI calibration through the differentiable implied volatility, one Adam
 step per replay of a captured hipGraph (torch.cuda.CUDAGraph is hipGraph on
-ROCm).  All arithmetic is in ``fv_svi_adam_step`` (three kernel launches,
+ROCm).  All arithmetic is in ``fv_svi_adam_step`` (four kernel launches,
 no allocation, no host synchronisation); this module only owns the device
 buffers (state and workspace), the capture and the replays.
 """

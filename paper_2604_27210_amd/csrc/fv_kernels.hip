@@ -81,13 +81,21 @@ struct GreekOut {
 // Largest workgroup the kernels are compiled for (8 waves).
 constexpr int kMaxBlock = 512;
 // Minimum resident waves per SIMD the solver kernels are register-allocated
-// for (2: up to 256 VGPRs, 3: 168, 4: 128, 6: 80).  The plain solver kernels
-// fit 6 without spilling (8 spills to scratch); their fused-Greeks variants
-// keep more live values and are held at 2 so that they do not spill.
-#ifndef FV_SOLVER_WAVES_PER_EU
-#define FV_SOLVER_WAVES_PER_EU 6
+// for (2: up to 256 VGPRs, 3: 168, 4: 128, 6: 80).  LBR runs at 4: at 6 it
+// is no faster, and its one-byte flag and status accesses (half a 128-byte
+// line per wave) then get fetched and written back twice as often (53 + 13
+// instead of 49 + 9 bytes per quote on the wide workload).  Halley, with
+// more steps per quote, is 2.5% faster at 6 (80 VGPRs, no spills).  The
+// fused-Greeks variants keep more live values and are held at 2 so that
+// they do not spill.
+#ifndef FV_LBR_WAVES_PER_EU
+#define FV_LBR_WAVES_PER_EU 4
 #endif
-#define FV_WAVES(GREEKS) ((GREEKS) ? 2 : FV_SOLVER_WAVES_PER_EU)
+#ifndef FV_HALLEY_WAVES_PER_EU
+#define FV_HALLEY_WAVES_PER_EU 6
+#endif
+#define FV_WAVES_LBR(GREEKS) ((GREEKS) ? 2 : FV_LBR_WAVES_PER_EU)
+#define FV_WAVES_HALLEY(GREEKS) ((GREEKS) ? 2 : FV_HALLEY_WAVES_PER_EU)
 // The ragged kernel keeps its CSR windows live across the solve; held to the
 // flat kernel's 4 waves per SIMD (<= 128 VGPRs).
 #ifndef FV_CHAINS_WAVES_PER_EU
@@ -126,7 +134,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_price(KQuotes q, fv_arg sigma, do
 // ------------------------------------------------------------- IV: LBR
 template <int MODEL, bool GREEKS, bool ARR>
 __global__ __launch_bounds__(kMaxBlock)
-__attribute__((amdgpu_waves_per_eu(FV_WAVES(GREEKS)))) void k_iv_lbr(KQuotes q, double* __restrict__ sig_out, uint8_t* __restrict__ st_out,
+__attribute__((amdgpu_waves_per_eu(FV_WAVES_LBR(GREEKS)))) void k_iv_lbr(KQuotes q, double* __restrict__ sig_out, uint8_t* __restrict__ st_out,
                          GreekOut g, int qpt) {
   const int64_t base = (int64_t)blockIdx.x * blockDim.x * qpt + threadIdx.x;
   for (int k = 0; k < qpt; ++k) {
@@ -185,6 +193,29 @@ __global__ __launch_bounds__(kMaxBlock) void k_lbr_trace(KQuotes q, uint32_t* __
   }
 }
 
+// Diagnostic twin of k_iv_halley: the number of Halley steps each quote
+// takes, with bit 8 set when it fails the convergence check (and would go
+// through the bisection fallback).
+template <int MODEL>
+__global__ __launch_bounds__(kMaxBlock) void k_halley_trace(KQuotes q, uint32_t* __restrict__ out,
+                                                            int qpt) {
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x * qpt + threadIdx.x;
+  for (int k = 0; k < qpt; ++k) {
+    const int64_t i = base + (int64_t)k * blockDim.x;
+    if (i >= q.n) return;
+    const double P = ld(q.price, i), fs = ld(q.fs, i), K = ld(q.K, i), T = ld(q.T, i),
+                 r = ld(q.r, i);
+    const double qy = MODEL == fv::kBlackScholesMerton ? ld(q.q, i) : 0.0;
+    const Reduced rd = fv::reduce_quote(MODEL, P, fs, K, T, r, qy, ldflag(q, i));
+    uint32_t code = 0xFFFFFFFFu;  // not solved (status != OK)
+    if (rd.status == fv::kQOk) {
+      const fv::HalleyState hs = fv::halley_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kHalleySteps);
+      code = (uint32_t)hs.steps | (hs.converged ? 0u : 0x100u);
+    }
+    out[i] = code;
+  }
+}
+
 // ------------------------------------------------------------- IV: Halley
 // LDS queue entry of a lane that failed the convergence check.
 struct Pending {
@@ -199,7 +230,7 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 
 template <int MODEL, bool GREEKS, bool ARR>
 __global__ __launch_bounds__(kMaxBlock)
-__attribute__((amdgpu_waves_per_eu(FV_WAVES(GREEKS)))) void k_iv_halley(KQuotes q, double* __restrict__ sig_out,
+__attribute__((amdgpu_waves_per_eu(FV_WAVES_HALLEY(GREEKS)))) void k_iv_halley(KQuotes q, double* __restrict__ sig_out,
                             uint8_t* __restrict__ st_out, GreekOut g, int qpt) {
   extern __shared__ unsigned char smem_raw[];
   Pending* queue = reinterpret_cast<Pending*>(smem_raw);
@@ -1089,6 +1120,23 @@ int fv_lbr_trace(int model, const fv_quotes* q, uint32_t* path_out, void* stream
     default: k_lbr_trace<2><<<grid, block, 0, s>>>(k, path_out, sh.qpt); break;
   }
   return launched("fv_lbr_trace");
+}
+
+int fv_halley_trace(int model, const fv_quotes* q, uint32_t* steps_out, void* stream) {
+  int rc = check_quotes(model, q);
+  if (rc) return rc;
+  if (q->n == 0) return FV_OK;
+  if (!steps_out) return fail(FV_E_INVALID_ARG, "steps_out is NULL");
+  const LaunchShape sh = shape_for(FV_KERNEL_IV_LBR, model, q->n);
+  const KQuotes k = to_k(q);
+  hipStream_t s = (hipStream_t)stream;
+  const dim3 grid = grid_for(q->n, sh), block(sh.block);
+  switch (model) {
+    case FV_MODEL_BLACK76: k_halley_trace<0><<<grid, block, 0, s>>>(k, steps_out, sh.qpt); break;
+    case FV_MODEL_BLACK_SCHOLES: k_halley_trace<1><<<grid, block, 0, s>>>(k, steps_out, sh.qpt); break;
+    default: k_halley_trace<2><<<grid, block, 0, s>>>(k, steps_out, sh.qpt); break;
+  }
+  return launched("fv_halley_trace");
 }
 
 int fv_implied_vol_chains(int solver, const fv_chains* c, double* sigma_out,

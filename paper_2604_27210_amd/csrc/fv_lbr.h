@@ -323,6 +323,7 @@ __host__ __device__ __attribute__((always_inline)) inline LbrResult lbr_solve(
 // ------------------------------------------------------- Halley path
 struct HalleyState {
   double s, lo, hi;
+  int steps;  // Halley steps taken
   bool converged;
 };
 
@@ -419,13 +420,16 @@ __host__ __device__ __attribute__((always_inline)) inline HalleyState halley_sol
   const double s_bs = kSqrt2Pi * beta;
   double s = x < 0.0 ? fmax(s_bs, -x * rsqrt(-2.0 * ln_beta)) : s_bs;
   double ds = 0.0, res = 0.0;
-  for (int k = 0; k < steps; ++k) {
+  int k = 0;
+  while (k < steps) {
     const double sn = halley_step(x, beta, bmax, ln_beta, logres, s, st, res);
     ds = sn - s;
     s = sn;
+    ++k;
     if (fabs(ds) <= kHalleyStepTol * s) break;
   }
   st.s = s;
+  st.steps = k;
   st.converged = fabs(ds) <= kHalleyStepTol * s && fabs(res) <= (logres ? 1e-2 : 1e-2 * beta) &&
                  s > 0.0 && __builtin_isfinite(s);
   return st;

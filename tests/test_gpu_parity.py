@@ -674,3 +674,38 @@ def test_subnormal_prices(fv, solver):
         assert len(res["status_bad"]) == 0 and len(res["value_bad"]) == 0, (
             res["value_bad"][:5], res["max_ratio"])
         assert res["n_ok"] >= 0.9 * len(Pq)
+
+
+def test_traces_and_sorted_order(fv):
+    """fv_lbr_trace and fv_halley_trace codes are well-formed (LBR: region
+    0..3, 2..4 steps; Halley: 1..8 steps, bit 8 for the bisection fallback;
+    0xFFFFFFFF exactly where the status is not OK), and solving the quotes
+    sorted by either code gives bitwise the same sigma per quote: the sorted
+    launches the census counts do the same work as the workload's own order."""
+    wl = W.bsm_wide(60_000, seed=17)
+    P = assemble_prices(wl)
+    ins = [dev(P), dev(wl.fs), dev(wl.K), dev(wl.T), dev(wl.r)]
+    fl, qq = dev(wl.flag, torch.int8), dev(wl.q)
+    for solver, trace in (("lbr", fv.lbr_trace), ("halley", fv.halley_trace)):
+        sig, st = fv.implied_vol("bsm", *ins, flag=fl, q=qq, solver=solver)
+        code = trace("bsm", *ins, flag=fl, q=qq)
+        c = host(code).astype(np.uint32)
+        ok = host(st) == 0
+        unsolved = c == 0xFFFFFFFF
+        # NOT_CONVERGED quotes were solved (their trace is a path code)
+        assert np.array_equal(unsolved, np.isin(host(st), [1, 2, 3, 4])), solver
+        cs = c[~unsolved]
+        if solver == "lbr":
+            assert np.all((cs >> 2 & 3) <= 2)
+        else:
+            assert np.all(((cs & 0xFF) >= 1) & ((cs & 0xFF) <= 8) & ((cs >> 9) == 0))
+            assert ((cs >> 8) & 1).mean() < 0.005  # the paper's fallback bound
+        order = torch.argsort(code.to(torch.int64))
+        sig2, st2 = fv.implied_vol("bsm", *[x.index_select(0, order).contiguous() for x in ins],
+                                   flag=fl.index_select(0, order).contiguous(),
+                                   q=qq.index_select(0, order).contiguous(), solver=solver)
+        inv = torch.empty_like(order)
+        inv[order] = torch.arange(order.numel(), device=order.device)
+        assert torch.equal(torch.nan_to_num(sig2[inv], -1.0), torch.nan_to_num(sig, -1.0)), solver
+        assert torch.equal(st2[inv], st), solver
+        assert ok.mean() > 0.97
