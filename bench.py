@@ -437,14 +437,17 @@ def extras(fv, torch, main_inputs):
     res = {}
     # 200 untimed steps of a throw-away calibrator first (sustained clock)
     calibrate_svi(SviCalibrator(*args, raw_from_natural(cal.theta0)), 200, graph=False)
-    for graph in (False, True):
+    # eager launches; one step per graph replay; ten steps per replay; the
+    # whole 200-step loop as one graph
+    for name, graph, k in (("eager", False, 1), ("graph", True, 1),
+                           ("graph_10_steps_per_replay", True, 10),
+                           ("graph_200_steps_per_replay", True, 200)):
         c = SviCalibrator(*args, raw_from_natural(cal.theta0))
-        r_ = calibrate_svi(c, 200, graph=graph)
+        r_ = calibrate_svi(c, 200, graph=graph, steps_per_replay=k)
         ok = torch.isfinite(iv_t)
         rmse = 100 * torch.sqrt(torch.mean((c.vols()[ok] - iv_t[ok]) ** 2)).item()
-        res["graph" if graph else "eager"] = {"steps_per_s": r_["steps_per_s"],
-                                              "final_rmse_vol_points": rmse,
-                                              "final_loss": float(c.losses()[-1])}
+        res[name] = {"steps_per_s": r_["steps_per_s"], "final_rmse_vol_points": rmse,
+                     "final_loss": float(c.losses()[-1])}
     # the oracle's final RMSE on the same problem (binary128 targets, numpy
     # replay of the 200 steps), stored by tests/golden/make_svi_calibration.py
     gold_path = os.path.join(ROOT, "tests", "golden", "svi_calibration_500.json")

@@ -268,7 +268,10 @@ int fv_svi_vols(const fv_svi_problem *p, const double *theta, double *sigma_out,
 /* Normalised Black function b(x, s, theta) (the evaluator underneath every
  * entry point): theta [e^{x/2} Phi(theta(x/s + s/2)) - e^{-x/2}
  * Phi(theta(x/s - s/2))].  x, s: device arrays [n] (s >= 0); flag: device
- * int8 [n] or NULL for calls.  out: [n]. */
+ * int8 [n] or NULL for calls.  out: [n].  Out of the money the result is
+ * within a few ulps of the exact b at the given x and s (the exponent
+ * -(x^2/s^2 + s^2/4)/2 is formed to twice the working precision), and below
+ * the normal range within a few units of the smallest subnormal. */
 int fv_normalised_black(int64_t n, const double *x, const double *s, const int8_t *flag,
                         double *out, void *stream);
 

@@ -1,6 +1,6 @@
-"""SVI calibration through the differentiable implied volatility, one Adam
-step per replay of a captured hipGraph (torch.cuda.CUDAGraph is hipGraph on
-ROCm).  All arithmetic is in ``fv_svi_adam_step`` (four kernel launches,
+"""SVI calibration through the differentiable implied volatility, one or
+more Adam steps per replay of a captured hipGraph (torch.cuda.CUDAGraph is
+hipGraph on ROCm).  All arithmetic is in ``fv_svi_adam_step`` (four kernel launches,
 no allocation, no host synchronisation); this module only owns the device
 buffers (state and workspace), the capture and the replays.
 """
@@ -57,6 +57,7 @@ class SviCalibrator:
         self.workspace = torch.empty(int(nws), dtype=torch.float64, device=dev)
         self.loss = torch.full((max_steps,), float("nan"), dtype=torch.float64, device=dev)
         self.graph = None
+        self.steps_per_replay = 0
 
     def step(self):
         N.check(N.load().fv_svi_adam_step(
@@ -65,13 +66,20 @@ class SviCalibrator:
             self.workspace.numel(), api._ptr(self.loss), self.loss.numel(), ctypes.c_void_p(api._stream_ptr())),
             "fv_svi_adam_step")
 
-    def capture(self):
-        """Capture one step into a graph (the state buffers are updated in
-        place by every replay).  The capture itself runs no step."""
+    def capture(self, steps_per_replay: int = 1):
+        """Capture `steps_per_replay` consecutive steps into one graph (the
+        state buffers are updated in place by every replay).  The capture
+        itself runs no step.  More than one step per replay spreads the
+        runtime's fixed cost of a graph launch over several steps."""
+        k = int(steps_per_replay)
+        if k < 1:
+            raise ValueError("steps_per_replay must be >= 1, got %r" % (steps_per_replay,))
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            self.step()
+            for _ in range(k):
+                self.step()
         self.graph = g
+        self.steps_per_replay = k
         return g
 
     def replay(self):
@@ -89,17 +97,25 @@ class SviCalibrator:
         return self.loss[:min(k, self.loss.numel())].cpu().numpy()
 
 
-def calibrate_svi(cal: SviCalibrator, steps: int = 200, graph: bool = True) -> dict:
-    """Run `steps` Adam steps (graph replays or eager launches) and time them."""
-    if graph and cal.graph is None:
-        cal.capture()
+def calibrate_svi(cal: SviCalibrator, steps: int = 200, graph: bool = True,
+                  steps_per_replay: int = 1) -> dict:
+    """Run `steps` Adam steps (graph replays of `steps_per_replay` steps
+    each, or eager launches) and time them."""
+    if graph:
+        if steps % steps_per_replay:
+            raise ValueError("steps (%d) must be a multiple of steps_per_replay (%d)"
+                             % (steps, steps_per_replay))
+        if cal.graph is None or cal.steps_per_replay != steps_per_replay:
+            cal.capture(steps_per_replay)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        if graph:
+    if graph:
+        for _ in range(steps // steps_per_replay):
             cal.replay()
-        else:
+    else:
+        for _ in range(steps):
             cal.step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"steps": steps, "seconds": dt, "steps_per_s": steps / dt, "graph": graph}
+    return {"steps": steps, "seconds": dt, "steps_per_s": steps / dt, "graph": graph,
+            "steps_per_replay": steps_per_replay if graph else 0}

@@ -617,7 +617,7 @@ __global__ void k_normalised_black(int64_t n, const double* __restrict__ x,
   // out-of-the-money side by parity: b(x, s, th) = b(-|x|, s) + intrinsic
   const double xo = -fabs(xi);
   const double bmax = exp(0.5 * xo);
-  const fv::NBlack nb = fv::normalised_black(xo, si, bmax);
+  const fv::NBlack nb = fv::normalised_black_t<0, true>(xo, si, bmax);
   double b = nb.b;
   // in the money: add the intrinsic th (e^{x/2} - e^{-x/2}) = th 2 sinh(x/2),
   // from expm1 so that small |x| keeps its relative precision

@@ -351,7 +351,14 @@ enum NbForm : int { kFormDifference = 0, kFormComplement = 1 };
 // one-step reciprocals, ~1e-8 relative in b and in b_max - b; 2 (the
 // boundary point of the initial guess) erfcx fit of degree 7 and a
 // degree-6 exp, ~1e-5.
-template <int P>
+// CE (compensated exponent, with P = 0): the exponent -(h^2 + t^2)/2 is
+// formed to twice the working precision and its low part carried into E.
+// Without it the rounding of h = x/s (a few ulps) is amplified by h^2 in
+// E: deep in the wing, where b is tiny, b is then accurate to its inputs'
+// conditioning (thousands of ulps at |h| ~ 40) rather than to a few ulps
+// of the exact b at the given x and s.  The solvers do not need it: there
+// the same error moves the root by only ~1/h^2 of it.
+template <int P, bool CE = false>
 __host__ __device__ inline NBlack normalised_black_t(double x, double s, double bmax) {
   constexpr bool LO = P >= 1;
   NBlack r;
@@ -372,8 +379,27 @@ __host__ __device__ inline NBlack normalised_black_t(double x, double s, double 
   }
   r.is = LO ? rcp_lo(s) : rcp(s);
   const double h = x * r.is, t = 0.5 * s;
-  const double ea = -0.5 * fma(h, h, t * t);
-  const double E = P == 0 ? fexp(ea) : (P == 1 ? fexp_lo(ea) : fexp_g(ea));
+  double ea = -0.5 * fma(h, h, t * t);
+  double E;
+  if (CE) {
+    // error-free transformations: no product may be contracted into a sum
+#pragma clang fp contract(off)
+    // x/s = h + hl with hl = (x - h s)/s (the residual is exact in an fma);
+    // h^2 = p + pl and t^2 = q + ql exactly; p + q = sm + se by two-sum
+    const double hl = fma(-h, s, x) * r.is;
+    const double p = h * h, pl = fma(h, h, -p) + 2.0 * h * hl;
+    const double q = t * t, ql = fma(t, t, -q);
+    const double sm = p + q;
+    const double bb = sm - p;
+    const double se = (p - (sm - bb)) + (q - bb);
+    ea = -0.5 * sm;
+    const double ea_lo = -0.5 * (se + (pl + ql));
+    const double E0 = fexp(ea);
+    E = fma(E0, ea_lo, E0);  // e^{ea + ea_lo} = e^{ea} (1 + ea_lo), |ea_lo| < 2^-52 |ea|
+    ea += ea_lo;
+  } else {
+    E = P == 0 ? fexp(ea) : (P == 1 ? fexp_lo(ea) : fexp_g(ea));
+  }
   r.bp = kInvSqrt2Pi * E;
   r.lnbp = ea - kLnSqrt2Pi;
   const double q1 = -(h + t) * kInvSqrt2, q2 = (t - h) * kInvSqrt2;

@@ -79,6 +79,29 @@ def test_graph_replay_equals_eager(fv, problem):
     assert int(b.step_count.item()) == 25
 
 
+def test_multi_step_graph_equals_eager(fv, problem):
+    """Five steps captured per graph, replayed five times, with eager work
+    and synchronisations of the program between the replays: bitwise the
+    eager trajectory after every replay."""
+    c, mat, target = problem
+    from paper_2604_27210_amd.calibrate import calibrate_svi
+    a = _calibrator(fv, c, target)
+    b = _calibrator(fv, c, target)
+    b.capture(5)
+    for rep in range(5):
+        calibrate_svi(a, 5, graph=False)
+        b.replay()
+        junk = torch.ones(1000, device=b.theta.device).cumsum(0)  # eager work between replays
+        torch.cuda.synchronize()
+        assert float(junk[-1]) == 1000.0
+        assert int(b.step_count.item()) == 5 * (rep + 1)
+        assert torch.equal(a.theta, b.theta), rep
+        assert torch.equal(a.m, b.m) and torch.equal(a.v, b.v), rep
+        assert np.array_equal(a.losses(), b.losses()), rep
+    with pytest.raises(ValueError):
+        calibrate_svi(b, 12, graph=True, steps_per_replay=5)
+
+
 def test_200_steps_match_oracle_replay(fv, problem):
     c, mat, target = problem
     from paper_2604_27210_amd.calibrate import calibrate_svi
