@@ -37,10 +37,10 @@ if ROOT not in sys.path:
 # The traffic figure is reported only while the kernel sources still hash to
 # ``source_sha256``; the FLOP figure is the algorithmic count of that source.
 LBR_PROFILE = {
-    "source_sha256": "9d6a064c8907ef57c9fcb6a73fdba4b5aad9d6c29fb70a5d3f4693ac2447f51a",
+    "source_sha256": "8f6c47e7e1f15d40b33be47864e1e2f345e118a4f129b00b8324b8dd617d3ef2",
     "flop_per_quote": 1120.2,
     "valu_per_quote": 1074.3,
-    "fetch_bytes_per_quote": 49.037,
+    "fetch_bytes_per_quote": 49.036,
     "write_bytes_per_quote": 9.009,
 }
 FP64_VECTOR_PEAK_TFLOPS = 78.6
@@ -323,18 +323,35 @@ def _graph_replay_us(torch, fn, reps=50):
     return _time(torch, g.replay, reps=reps, warm=3) * 1e3
 
 
-def extras(fv, torch, main_inputs):
+def extras(fv, torch, main_inputs, sig_true):
     """Secondary measurements beside the headline: the Halley path on the
-    same batch, the small batch's latency, ragged chains (one persistent
-    launch vs the flat kernel on expanded arrays vs one launch per chain),
-    forward+backward of the differentiable IV, and the hipGraph calibration
-    loop (graph replay vs eager launches)."""
+    same batch, pricing and Greeks on it against a plain device copy, the
+    small batch's latency, ragged chains (one persistent launch vs the flat
+    kernel on expanded arrays vs one launch per chain), forward+backward of
+    the differentiable IV, and the hipGraph calibration loop (graph replay
+    vs eager launches)."""
     from paper_2604_27210_amd import workloads as W
     from paper_2604_27210_amd.calibrate import SviCalibrator, calibrate_svi, raw_from_natural
     d = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dt)
     out = {}
     P, S, K, T, r, q, flag = main_inputs
     n = P.numel()
+    # the memory-heavy paths against the HBM rate a plain device copy reaches
+    # on this box (the same bytes as the pricing call moves)
+    src = torch.empty(n * 57 // 16, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    copy_ms = _time(torch, lambda: dst.copy_(src), reps=50)
+    copy_gbs = 2 * src.numel() * 8 / (copy_ms * 1e-3) / 1e9
+    del src, dst
+    out["hbm_device_copy_GBs"] = copy_gbs
+    for name, fn, nbytes in (
+            ("price_bsm", lambda: fv.price("bsm", S, K, T, r, sig_true, flag=flag, q=q), 49 + 8),
+            ("greeks_bsm", lambda: fv.greeks("bsm", S, K, T, r, sig_true, flag=flag, q=q),
+             49 + 40)):
+        ms = _time(torch, fn, reps=50)
+        gbs = nbytes * n / (ms * 1e-3) / 1e9
+        out[name] = {"ms": ms, "per_s": n / ms * 1e3, "algorithmic_GBs": gbs,
+                     "frac_of_device_copy": gbs / copy_gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
     ms = _time(torch, lambda: fv.implied_vol("bsm", P, S, K, T, r, flag=flag, q=q, solver="halley"))
     out["halley_wide_bsm"] = {"ms": ms, "implied_vols_per_s": n / ms * 1e3}
     # the binary32 Halley path on the same quotes rounded to float32
@@ -748,7 +765,8 @@ def main():
         "roofline": roof,
     }
     if not a.no_extras:
-        out["extras"] = extras(fv, torch, (P, S, K, T, r, q, flag))
+        out["extras"] = extras(fv, torch, (P, S, K, T, r, q, flag),
+                               torch.from_numpy(wl.sigma_true).cuda())
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, P.cpu().numpy(), a.cpu_sample)
         out.setdefault("extras", {})["host_fp64_lbr"] = host_fp64_lbr(wl, P.cpu().numpy(), wl.n)
