@@ -33,8 +33,8 @@
  *    rho = dP/dr (Black-76: at fixed F).
  *  - Not thread-safe across concurrent calls that share output buffers;
  *    otherwise calls from several host threads are independent, except that
- *    fv_set_launch and fv_autotune change process-wide launch shapes and
- *    must not run while another thread launches.
+ *    fv_set_launch, fv_autotune and fv_set_halley_steps change process-wide
+ *    settings and must not run while another thread launches.
  */
 #ifndef FASTVOL_H
 #define FASTVOL_H
@@ -146,8 +146,9 @@ typedef struct {
 
 /* Implied volatility in binary32 arithmetic with the Halley path (paper
  * section 2.2: the throughput solver for label pipelines that train in
- * float32): Brenner-Subrahmanyam start, at most 8 Halley steps, bisection
- * for the quotes that fail the convergence check, all in float.
+ * float32): Brenner-Subrahmanyam start, at most 8 Halley steps (the
+ * fv_set_halley_steps limit), bisection for the quotes that fail the
+ * convergence check, all in float.
  * sigma_out: float [n] (required); status_out: uint8 [n] or NULL.  Statuses
  * as for fv_implied_vol; FV_Q_NOT_CONVERGED (sigma NaN) also marks a quote
  * whose normalised out-of-the-money price beta = P_undiscounted/sqrt(F K)
@@ -287,11 +288,29 @@ int fv_lbr_trace(int model, const fv_quotes *q, uint32_t *path_out, void *stream
 
 /* Diagnostic: the Halley steps each quote takes as fv_implied_vol(...,
  * FV_SOLVER_HALLEY, ...) solves it (paper section 2.2, the throughput path).
- * steps_out: uint32 [n]; bits 0-7 the number of Halley steps (1..8),
- * bit 8 set when the quote fails the convergence check and goes through
- * the bisection fallback; 0xFFFFFFFF for quotes whose status is not
- * FV_Q_OK.  Used to group quotes by work, e.g. to measure divergence. */
+ * steps_out: uint32 [n]; bits 0-7 the number of Halley steps (1 up to the
+ * fv_set_halley_steps limit, 8 by default), bit 8 set when the quote fails
+ * the convergence check and goes through the bisection fallback; 0xFFFFFFFF
+ * for quotes whose status is not FV_Q_OK.  Used to group quotes by work,
+ * e.g. to measure divergence. */
 int fv_halley_trace(int model, const fv_quotes *q, uint32_t *steps_out, void *stream);
+
+/* The Halley path's step limit (paper section 2.2: a fixed number of Halley
+ * steps, then bisection for the quotes that fail the convergence check).
+ * Every Halley launch (fv_implied_vol with FV_SOLVER_HALLEY, the ragged
+ * chains, fv_implied_vol_f32, fv_halley_trace) reads it when it is
+ * enqueued; default 8.  In binary64 the iteration starts from the LBR
+ * path's initial guess and its first step is at guess precision, so a quote
+ * never stops before its second step: a limit of 1 sends every solvable
+ * quote to the fallback, 2 the quotes that need a third step (binary32
+ * starts from the Brenner-Subrahmanyam form and may stop after any step).
+ * Results stay within the Halley tolerance at any
+ * limit (the fallback bisects to 1e-13 relative); a lower limit only moves
+ * work to the slower bisection, which makes it a way to exercise that path.
+ * steps in [1, 64], FV_E_INVALID_ARG otherwise (the limit in force is
+ * kept).  Process-wide, like fv_set_launch. */
+int fv_set_halley_steps(int steps);
+int fv_get_halley_steps(void);
 
 /* Launch-shape control.  fv_set_launch(kernel, block, quotes_per_thread)
  * overrides the launch shape of one kernel family (FV_KERNEL_*); block must

@@ -11,7 +11,7 @@ from . import _native  # noqa: F401
 
 __all__ = ["price", "implied_vol", "implied_vol_f32", "greeks", "implied_vol_backward", "implied_vol_chains",
            "price_backward", "price_autograd", "lbr_trace", "halley_trace",
-           "normalised_black", "set_launch", "get_launch", "autotune", "version",
+           "set_halley_steps", "get_halley_steps", "normalised_black", "set_launch", "get_launch", "autotune", "version",
            "autotune_all", "launch_shape", "save_tuning", "load_tuning", "reset_tuning",
            "IVFunction", "implied_vol_autograd"]
 
@@ -20,7 +20,8 @@ def __getattr__(name):
     if name in ("price", "implied_vol", "implied_vol_f32", "greeks", "implied_vol_backward", "implied_vol_chains",
                 "normalised_black", "set_launch", "get_launch", "autotune", "version",
                 "autotune_all", "launch_shape", "save_tuning", "load_tuning", "reset_tuning",
-                "price_backward", "lbr_trace", "halley_trace"):
+                "price_backward", "lbr_trace", "halley_trace", "set_halley_steps",
+                "get_halley_steps"):
         from . import api
         return getattr(api, name)
     if name in ("IVFunction", "implied_vol_autograd", "PriceFunction", "price_autograd"):

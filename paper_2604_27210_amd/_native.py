@@ -66,7 +66,8 @@ class FvSviProblem(ctypes.Structure):
 
 
 EXPORTS = ["fv_price", "fv_implied_vol", "fv_implied_vol_f32", "fv_greeks", "fv_implied_vol_backward", "fv_price_backward",
-           "fv_implied_vol_chains", "fv_normalised_black", "fv_lbr_trace", "fv_halley_trace", "fv_set_launch", "fv_get_launch",
+           "fv_implied_vol_chains", "fv_normalised_black", "fv_lbr_trace", "fv_halley_trace", "fv_set_halley_steps", "fv_get_halley_steps",
+           "fv_set_launch", "fv_get_launch",
            "fv_autotune", "fv_launch_shape", "fv_tuning_reset", "fv_tuning_save", "fv_tuning_load",
            "fv_svi_workspace_size", "fv_svi_adam_step", "fv_svi_adam_step_noalloc", "fv_svi_vols", "fv_last_error", "fv_version"]
 
@@ -99,6 +100,8 @@ def load():
     lib.fv_normalised_black.argtypes = [I64, V, V, V, V, V]
     lib.fv_lbr_trace.argtypes = [I, P(FvQuotes), V, V]
     lib.fv_halley_trace.argtypes = [I, P(FvQuotes), V, V]
+    lib.fv_set_halley_steps.argtypes = [I]
+    lib.fv_get_halley_steps.argtypes = []
     lib.fv_svi_workspace_size.argtypes = [P(FvSviProblem)]
     lib.fv_svi_workspace_size.restype = I64
     lib.fv_svi_adam_step.argtypes = [P(FvSviProblem), V, V, V, V, V, V, I64, V, I64, V]

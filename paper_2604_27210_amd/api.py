@@ -327,6 +327,15 @@ def halley_trace(model, price, fs, K, T, r, flag="c", q=None, stream=None) -> to
     return out
 
 
+def set_halley_steps(steps: int) -> None:
+    """Halley steps before the bisection fallback (fv_set_halley_steps)."""
+    N.check(N.load().fv_set_halley_steps(int(steps)), "fv_set_halley_steps")
+
+
+def get_halley_steps() -> int:
+    return int(N.load().fv_get_halley_steps())
+
+
 def set_launch(kernel, block: int, quotes_per_thread: int) -> None:
     k = N.KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     N.check(N.load().fv_set_launch(k, int(block), int(quotes_per_thread)), "fv_set_launch")

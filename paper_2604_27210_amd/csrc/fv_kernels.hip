@@ -18,6 +18,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -54,6 +55,7 @@ struct KQuotes {
   fv_arg price, fs, K, T, r, q;
   const int8_t* flag;
   int8_t flag_value;
+  int hsteps;  // Halley steps before the bisection fallback (fv_set_halley_steps)
 };
 
 // A field's value for quote i: its array entry, or its broadcast value.
@@ -105,7 +107,8 @@ constexpr int kMaxBlock = 512;
 constexpr int kLbrMinSteps = 2;
 constexpr int kLbrMaxSteps = 4;
 constexpr double kLbrStepTol = 1e-6;
-constexpr int kHalleySteps = 8;
+constexpr int kHalleySteps = 8;  // the paper's count; the default of fv_set_halley_steps
+constexpr int kMaxHalleySteps = 64;
 constexpr double kBisectTol = 1e-13;
 
 // ------------------------------------------------------------- price
@@ -209,7 +212,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_halley_trace(KQuotes q, uint32_t*
     const Reduced rd = fv::reduce_quote(MODEL, P, fs, K, T, r, qy, ldflag(q, i));
     uint32_t code = 0xFFFFFFFFu;  // not solved (status != OK)
     if (rd.status == fv::kQOk) {
-      const fv::HalleyState hs = fv::halley_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kHalleySteps);
+      const fv::HalleyState hs = fv::halley_solve(rd.x, rd.beta, rd.bmax, rd.lnb, q.hsteps);
       code = (uint32_t)hs.steps | (hs.converged ? 0u : 0x100u);
     }
     out[i] = code;
@@ -254,7 +257,7 @@ __attribute__((amdgpu_waves_per_eu(FV_WAVES_HALLEY(GREEKS)))) void k_iv_halley(K
       uint8_t st = rd.status;
       double sg = st == fv::kQAtIntrinsic ? 0.0 : __builtin_nan("");
       if (st == fv::kQOk) {
-        hs = fv::halley_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kHalleySteps);
+        hs = fv::halley_solve(rd.x, rd.beta, rd.bmax, rd.lnb, q.hsteps);
         sg = hs.s * rd.isqrtT;
         fail = !hs.converged;
       }
@@ -326,6 +329,7 @@ struct KQuotes32 {
   fv_arg_f32 price, fs, K, T, r, q;
   const int8_t* flag;
   int8_t flag_value;
+  int hsteps;
 };
 
 __device__ __forceinline__ float ld32(const fv_arg_f32& a, int64_t i) {
@@ -364,7 +368,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) 
       const uint8_t st = rd.status;
       float sg = st == fv::kQAtIntrinsic ? 0.0f : __builtin_nanf("");
       if (st == fv::kQOk) {
-        hs = fv32::halley_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kHalleySteps);
+        hs = fv32::halley_solve(rd.x, rd.beta, rd.bmax, rd.lnb, q.hsteps);
         sg = hs.s / rd.sqrtT;
         fail = !hs.converged;
       }
@@ -509,6 +513,7 @@ struct KChains {
   const int64_t* mat_quote_off;
   const double *F, *r, *T, *price, *K;
   const int8_t* flag;
+  int hsteps;
 };
 
 // Ragged-chain kernel: one launch over the CSR offsets, one wave per 64
@@ -562,7 +567,7 @@ __attribute__((amdgpu_waves_per_eu(FV_CHAINS_WAVES_PER_EU))) void k_iv_chains(
           sg = res.s * rd.isqrtT;
           if (!res.converged) st = fv::kQNotConverged;
         } else {
-          hs = fv::halley_solve(rd.x, rd.beta, rd.bmax, rd.lnb, kHalleySteps);
+          hs = fv::halley_solve(rd.x, rd.beta, rd.bmax, rd.lnb, c.hsteps);
           sg = hs.s * rd.isqrtT;
           fail = !hs.converged;
         }
@@ -752,6 +757,10 @@ int check_quotes(int model, const fv_quotes* q) {
   return FV_OK;
 }
 
+// Maximum Halley steps before a quote goes to the bisection fallback
+// (fv_set_halley_steps); read by every launch of a Halley kernel.
+std::atomic<int> g_halley_steps{kHalleySteps};
+
 KQuotes to_k(const fv_quotes* q) {
   KQuotes k;
   k.n = q->n;
@@ -763,6 +772,7 @@ KQuotes to_k(const fv_quotes* q) {
   k.q = q->q;
   k.flag = q->flag;
   k.flag_value = q->flag_value;
+  k.hsteps = g_halley_steps.load(std::memory_order_relaxed);
   return k;
 }
 
@@ -930,6 +940,15 @@ int fv_set_launch(int kernel, int block, int qpt) {
   return FV_OK;
 }
 
+int fv_set_halley_steps(int steps) {
+  if (steps < 1 || steps > kMaxHalleySteps)
+    return fail(FV_E_INVALID_ARG, "Halley steps outside [1, 64]");
+  g_halley_steps.store(steps, std::memory_order_relaxed);
+  return FV_OK;
+}
+
+int fv_get_halley_steps(void) { return g_halley_steps.load(std::memory_order_relaxed); }
+
 int fv_get_launch(int kernel, int* block, int* qpt) {
   if (kernel < 0 || kernel >= FV_KERNEL_COUNT || !block || !qpt)
     return fail(FV_E_INVALID_ARG, "kernel id or NULL output");
@@ -1030,6 +1049,7 @@ int fv_implied_vol_f32(int model, const fv_quotes_f32* q, float* sigma_out,
   k.q = q->q;
   k.flag = q->flag;
   k.flag_value = q->flag_value;
+  k.hsteps = g_halley_steps.load(std::memory_order_relaxed);
   const LaunchShape sh = shape_for(FV_KERNEL_IV_HALLEY_F32, model, q->n);
   const dim3 grid = grid_for(q->n, sh), block(sh.block);
   const size_t lds = sizeof(Pending32) * (size_t)sh.block * sh.qpt;
@@ -1167,6 +1187,7 @@ int fv_implied_vol_chains(int solver, const fv_chains* c, double* sigma_out,
   k.price = c->price;
   k.K = c->K;
   k.flag = c->flag;
+  k.hsteps = g_halley_steps.load(std::memory_order_relaxed);
   const LaunchShape sh = shape_for(FV_KERNEL_CHAINS, FV_MODEL_BLACK76, k.n);
   // one wave per 64 consecutive quotes, blockDim/64 waves per workgroup; the
   // quote count is capped (kMaxQuotes) so that the grid fits

@@ -356,22 +356,30 @@ __host__ __device__ inline double ln_nb(const NBlack& nb) {
 //    the root of the leading-order form);
 //  * a bracket [lo, hi] from the sign of the residual keeps every iterate
 //    inside; a step that would leave it bisects instead (geometrically).
-__host__ __device__ __attribute__((always_inline)) inline double halley_step(
+// P is the evaluation's precision level (normalised_black_t).  Only a
+// full-precision residual (P = 0) moves the bracket: near the root the
+// sign of a guess-precision residual is not reliable.
+template <int P>
+__host__ __device__ __attribute__((always_inline)) inline double halley_step_t(
     double x, double beta, double bmax, double ln_beta, bool logres, double s, HalleyState& st,
     double& res) {
-  const NBlack nb = normalised_black(x, s, bmax);
+  const NBlack nb = normalised_black_t<P>(x, s, bmax);
   const double is0 = nb.is;
   const double eta = x * x * is0 * is0 * is0 - 0.25 * s;  // b''/b'
   double sn;
   if (logres) {
     res = ln_nb(nb) - ln_beta;
-    if (res < 0.0) st.lo = s; else st.hi = s;
+    if (P == 0) {
+      if (res < 0.0) st.lo = s; else st.hi = s;
+    }
     const double lam = rcp(nb.ratio);  // b'/b
     const double nu = -res * nb.ratio;
     sn = s + nu * rcp_lo(1.0 + 0.5 * (eta - lam) * nu);
   } else {
     res = nb.b - beta;
-    if (res < 0.0) st.lo = s; else st.hi = s;
+    if (P == 0) {
+      if (res < 0.0) st.lo = s; else st.hi = s;
+    }
     const double nu = -res * rcp(nb.bp);
     const double hf = rcp_lo(1.0 + 0.5 * eta * nu);
     sn = s + nu * hf;
@@ -397,19 +405,24 @@ __host__ __device__ __attribute__((always_inline)) inline double halley_step(
   return sn;
 }
 
-// Start: the larger of the Brenner-Subrahmanyam at-the-money form
-// s0 = sqrt(2 pi) beta (b(0, s) ~ s/sqrt(2 pi)) and, away from the money,
-// the root of the leading-order wing form ln b ~ -x^2/(2 s^2),
-// s0 = |x|/sqrt(-2 ln beta); b rises in s and both forms undershoot the
-// root where they do not hold, so the larger is the closer.  Then at most
-// `steps` Halley steps.  Halley converges cubically: once a step is below
-// 1e-6 s the iterate it produced is within ~1e-18 of the root, so a lane
-// stops there (a wave whose lanes have all stopped leaves the loop early)
-// instead of spending one more step to confirm it.  Converged: the last
-// step below 1e-6 s, the residual before it within 1e-2 relative (a sanity
-// check against a stall where b' vanishes; near the root the residual is
-// the step times s b'/b, at most 1e-6 h^2), and a positive finite s.
-constexpr double kHalleyStepTol = 1e-6;
+// Start: the four-region initial guess of the LBR path (a few percent from
+// the root at worst), or, where it is not a positive finite number, the
+// larger of the Brenner-Subrahmanyam at-the-money form s0 = sqrt(2 pi) beta
+// and the root |x|/sqrt(-2 ln beta) of the leading-order wing form
+// ln b ~ -x^2/(2 s^2).  Then at most `steps` Halley steps, the first at
+// guess precision (from ~1e-2 it lands ~1e-6 from the root, far above that
+// evaluation's error), every later one at full precision.  Halley converges
+// cubically: after a step below 1e-5 s the error left is about
+// kc (1e-5)^3 s, where the error constant kc = (eta s)^2/12 + h^2/2 +
+// s^2/24 is up to about 130 on the wide workload (|h| <= 6), and below
+// 1e-8 s up to |h| of about 100 (beyond |h| ~ 37 the root is solved on the
+// nearly linear logarithmic residual).  So a lane stops at the first full-
+// precision step below 1e-5 s (a wave whose lanes have all stopped leaves
+// the loop early).  Converged: that stop, the residual before the last step
+// within 1e-2 relative (a sanity check against a stall where b' vanishes;
+// near the root the residual is the step times s b'/b, at most 1e-5 h^2),
+// and a positive finite s.
+constexpr double kHalleyStepTol = 1e-5;
 
 __host__ __device__ __attribute__((always_inline)) inline HalleyState halley_solve(
     double x, double beta, double bmax, double ln_beta, int steps) {
@@ -417,21 +430,28 @@ __host__ __device__ __attribute__((always_inline)) inline HalleyState halley_sol
   st.lo = 0.0;
   st.hi = 1e300;
   const bool logres = ln_beta < kLnBetaLogResidual;
-  const double s_bs = kSqrt2Pi * beta;
-  double s = x < 0.0 ? fmax(s_bs, -x * rsqrt(-2.0 * ln_beta)) : s_bs;
+  int region;
+  double s = lbr_initial_guess(x, beta, bmax, ln_beta, &region, nullptr);
+  if (!(s > 0.0 && s < 1e300)) {
+    const double s_bs = kSqrt2Pi * beta;
+    s = x < 0.0 ? fmax(s_bs, -x * rsqrt(-2.0 * ln_beta)) : s_bs;
+  }
   double ds = 0.0, res = 0.0;
+  bool stop = false;
   int k = 0;
   while (k < steps) {
-    const double sn = halley_step(x, beta, bmax, ln_beta, logres, s, st, res);
+    const double sn = k == 0 ? halley_step_t<1>(x, beta, bmax, ln_beta, logres, s, st, res)
+                             : halley_step_t<0>(x, beta, bmax, ln_beta, logres, s, st, res);
     ds = sn - s;
     s = sn;
     ++k;
-    if (fabs(ds) <= kHalleyStepTol * s) break;
+    stop = k >= 2 && fabs(ds) <= kHalleyStepTol * s;
+    if (stop) break;
   }
   st.s = s;
   st.steps = k;
-  st.converged = fabs(ds) <= kHalleyStepTol * s && fabs(res) <= (logres ? 1e-2 : 1e-2 * beta) &&
-                 s > 0.0 && __builtin_isfinite(s);
+  st.converged = stop && fabs(res) <= (logres ? 1e-2 : 1e-2 * beta) && s > 0.0 &&
+                 __builtin_isfinite(s);
   return st;
 }
 

@@ -192,3 +192,19 @@ def test_svi_workspace_size_and_small_workspace(lib):
         rc = lib.fv_svi_adam_step(ctypes.byref(prob), v, v, v, v, v, v, need - 1, None, 0, None)
         assert rc == N.FV_E_INVALID_ARG
         assert b"workspace" in lib.fv_last_error()
+
+
+def test_halley_step_limit_setting(lib):
+    """fv_set_halley_steps keeps the limit in [1, 64] and rejects anything
+    else without changing the limit in force (host-side only, no launch)."""
+    lib.fv_set_halley_steps.argtypes = [ctypes.c_int]
+    assert lib.fv_get_halley_steps() == 8
+    try:
+        for bad in (0, -1, 65):
+            assert lib.fv_set_halley_steps(bad) == -1
+            assert lib.fv_get_halley_steps() == 8
+        for good in (1, 2, 64):
+            assert lib.fv_set_halley_steps(good) == 0
+            assert lib.fv_get_halley_steps() == good
+    finally:
+        assert lib.fv_set_halley_steps(8) == 0

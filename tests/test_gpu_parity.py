@@ -709,3 +709,74 @@ def test_traces_and_sorted_order(fv):
         assert torch.equal(torch.nan_to_num(sig2[inv], -1.0), torch.nan_to_num(sig, -1.0)), solver
         assert torch.equal(st2[inv], st), solver
         assert ok.mean() > 0.97
+
+
+@pytest.fixture
+def halley_limit(fv):
+    """Sets the Halley step limit for one test and restores the default."""
+    def set_(k):
+        fv.set_halley_steps(k)
+    yield set_
+    fv.set_halley_steps(8)
+
+
+@pytest.mark.parametrize("limit", [1, 2])
+def test_halley_fallback_forced_by_step_limit(fv, halley_limit, limit):
+    """The bisection fallback and the Greeks of the quotes it solves, with the
+    Halley step limit lowered from the host so that the LDS queue is busy:
+    limit 1 sends every solvable quote to it, limit 2 the quotes that need a
+    third step (most waves then hold both kinds).  The trace marks exactly
+    those quotes; the implied volatility stays within the Halley tolerance of
+    the oracle and the fused Greeks within theirs, element by element."""
+    wl = W.bsm_diff(50_000, seed=4)
+    P = assemble_prices(wl)
+    halley_limit(limit)
+    assert fv.get_halley_steps() == limit
+    q = dev(wl.q)
+    code = host(fv.halley_trace("bsm", dev(P), dev(wl.fs), dev(wl.K), dev(wl.T), dev(wl.r),
+                                flag=dev(wl.flag, torch.int8), q=q)).astype(np.uint32)
+    solved = code != 0xFFFFFFFF
+    fell = ((code[solved] >> 8) & 1) == 1
+    steps = code[solved] & 0xFF
+    # the first step is at guess precision, so no quote stops before its
+    # second: every solvable quote runs the whole (lowered) limit
+    assert np.all(steps == limit)
+    if limit == 1:
+        assert fell.all()
+    else:
+        assert 0.01 < fell.mean() < 0.99, fell.mean()
+    sig, st, gk = run_iv(fv, wl, P, "halley", greeks=True)
+    res = compare_iv("bsm", "halley", P, wl.fs, wl.K, wl.T, wl.r, wl.q, wl.flag, host(sig),
+                     host(st))
+    _report("halley-limit-%d" % limit, res)
+    assert len(res["status_bad"]) == 0 and len(res["nan_bad"]) == 0
+    assert len(res["value_bad"]) == 0, (res["value_bad"][:5], res["max_ratio"])
+    st, sg = host(st), host(sig)
+    i = np.where(st == 0)[0]
+    assert len(i) > 0.999 * len(st)
+    bad, worst = greeks_bad("bsm", wl.fs[i], wl.K[i], wl.T[i], wl.r[i], wl.q[i], sg[i],
+                            wl.flag[i], {k: host(v)[i] for k, v in gk.items()})
+    print("halley-limit-%d greeks: max err/tol %.3g" % (limit, worst))
+    for name in GREEK_NAMES:
+        assert len(bad[name]) == 0, (name, bad[name][:5])
+
+
+def test_chains_halley_fallback_matches_flat(fv, halley_limit):
+    """Ragged chains through the Halley path with the step limit at 2 (the
+    chain kernel's own LDS queue busy): bitwise the flat Halley kernel on
+    the expanded arrays under the same limit."""
+    ch = W.b76_chains(40, seed=3)
+    flat = ch.flatten()
+    P = assemble_prices(flat)
+    halley_limit(2)
+    s_c, st_c = fv.implied_vol_chains(dev(ch.chain_mat_off, torch.int64),
+                                      dev(ch.mat_quote_off, torch.int64), dev(ch.F), dev(ch.r),
+                                      dev(ch.T), dev(P), dev(ch.K), dev(ch.flag, torch.int8),
+                                      solver="halley")
+    s_f, st_f = fv.implied_vol("black76", dev(P), dev(flat.fs), dev(flat.K), dev(flat.T),
+                               dev(flat.r), flag=dev(flat.flag, torch.int8), solver="halley")
+    code = host(fv.halley_trace("black76", dev(P), dev(flat.fs), dev(flat.K), dev(flat.T),
+                                dev(flat.r), flag=dev(flat.flag, torch.int8))).astype(np.uint32)
+    assert (((code >> 8) & 1) == 1).mean() > 0.01
+    assert torch.equal(st_c, st_f)
+    assert torch.equal(torch.nan_to_num(s_c, -1.0), torch.nan_to_num(s_f, -1.0))
