@@ -37,10 +37,10 @@ if ROOT not in sys.path:
 # The traffic figure is reported only while the kernel sources still hash to
 # ``source_sha256``; the FLOP figure is the algorithmic count of that source.
 LBR_PROFILE = {
-    "source_sha256": "8f6c47e7e1f15d40b33be47864e1e2f345e118a4f129b00b8324b8dd617d3ef2",
+    "source_sha256": "40a0b3ac56cab4fda36e6c195c1b31bfaf5a6a36c717e5aea073abf7fcad5214",
     "flop_per_quote": 1120.2,
     "valu_per_quote": 1074.3,
-    "fetch_bytes_per_quote": 49.036,
+    "fetch_bytes_per_quote": 49.037,
     "write_bytes_per_quote": 9.009,
 }
 FP64_VECTOR_PEAK_TFLOPS = 78.6
