@@ -718,7 +718,7 @@ struct LaunchShape {
 // the solvers); fv_autotune re-derives them for other shapes of work.
 LaunchShape g_shape[FV_KERNEL_COUNT] = {
     {256, 2},  // price
-    {128, 4},  // IV LBR
+    {64, 1},   // IV LBR
     {128, 4},  // IV Halley
     {256, 1},  // Greeks
     {128, 4},  // backward
