@@ -37,11 +37,11 @@ if ROOT not in sys.path:
 # The traffic figure is reported only while the kernel sources still hash to
 # ``source_sha256``; the FLOP figure is the algorithmic count of that source.
 LBR_PROFILE = {
-    "source_sha256": "40a0b3ac56cab4fda36e6c195c1b31bfaf5a6a36c717e5aea073abf7fcad5214",
+    "source_sha256": "f0c99f7ef46b5f3b62226c9b79f28eee00e7d5a1ccd7b9134ff6cbab5fbf87e5",
     "flop_per_quote": 1120.2,
-    "valu_per_quote": 1074.3,
-    "fetch_bytes_per_quote": 49.037,
-    "write_bytes_per_quote": 9.009,
+    "valu_per_quote": 1108.8,
+    "fetch_bytes_per_quote": 50.037,
+    "write_bytes_per_quote": 9.000,
 }
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 # VALU issue capacity at the nominal clock: 256 CUs x 4 SIMDs x 16 lanes,
