@@ -55,7 +55,7 @@ typedef enum {
 
 typedef enum {
     FV_SOLVER_LBR = 0,     /* rational guess + Householder(3): reference grade */
-    FV_SOLVER_HALLEY = 1   /* Halley x8 + bisection fallback: throughput path  */
+    FV_SOLVER_HALLEY = 1   /* Halley (<= 8 steps) + bisection fallback        */
 } fv_solver;
 
 typedef enum {

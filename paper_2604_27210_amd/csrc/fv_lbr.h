@@ -5,9 +5,12 @@
 //  * the "Let's Be Rational" path: boundary points of the normalised Black
 //    function, a four-region rational initial guess and Householder(3)
 //    steps on a three-branch transformed objective;
-//  * the Halley path: a Brenner-Subrahmanyam at-the-money start, a fixed
-//    number of Halley steps on the direct residual and a bisection fallback
-//    for the quotes that fail a convergence check.
+//  * the Halley path: a fixed number of Halley steps on the direct residual
+//    and a bisection fallback for the quotes that fail a convergence check.
+//    The paper starts it from the Brenner-Subrahmanyam at-the-money form;
+//    here it starts from the LBR path's initial guess (that form remains
+//    the fallback start), which cuts the steps a wave runs from about six
+//    to three on wide-wing batches.
 // Both work on the reduced problem "out-of-the-money call, x <= 0,
 // 0 < beta < b_max = e^{x/2}" and return the total volatility s = sigma
 // sqrt(T).
