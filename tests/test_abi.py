@@ -208,3 +208,22 @@ def test_halley_step_limit_setting(lib):
             assert lib.fv_get_halley_steps() == good
     finally:
         assert lib.fv_set_halley_steps(8) == 0
+
+
+def test_kernel_code_hash_ignores_comments_only():
+    """The hash that ties the bench's stored counter figures to the kernel
+    sources changes with the code, not with comments or layout (string
+    literals are kept verbatim, including a // inside one)."""
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    a = 'int f(int x) {\n  return x + 1;  // one\n}\nconst char* p = "a // b";\n'
+    b = '/* header */\nint f(int x)\n{ return x + 1; }\n// trailing\nconst char* p = "a // b";'
+    c = 'int f(int x) {\n  return x + 2;\n}\nconst char* p = "a // b";\n'
+    d = 'int f(int x) {\n  return x + 1;\n}\nconst char* p = "a /* b";\n'
+    ca = bench._code_only(a)
+    assert ca == bench._code_only(b)
+    assert ca != bench._code_only(c)
+    assert ca != bench._code_only(d)
+    assert '"a // b"' in ca
+    assert len(bench.kernel_source_sha256()) == 64
