@@ -86,10 +86,9 @@ constexpr int kMaxBlock = 512;
 // for (2: up to 256 VGPRs, 3: 168, 4: 128, 6: 80).  LBR runs at 4: at 6 it
 // is no faster, and its one-byte flag and status accesses (half a 128-byte
 // line per wave) then get fetched and written back twice as often (53 + 13
-// instead of 49 + 9 bytes per quote on the wide workload).  Halley, with
-// more steps per quote, is 2.5% faster at 6 (80 VGPRs, no spills).  The
-// fused-Greeks variants keep more live values and are held at 2 so that
-// they do not spill.
+// instead of 49 + 9 bytes per quote on the wide workload).  The Halley
+// kernels, at 80 VGPRs without spills, run 6.  The fused-Greeks variants
+// keep more live values and are held at 2 so that they do not spill.
 #ifndef FV_LBR_WAVES_PER_EU
 #define FV_LBR_WAVES_PER_EU 4
 #endif
@@ -98,8 +97,8 @@ constexpr int kMaxBlock = 512;
 #endif
 #define FV_WAVES_LBR(GREEKS) ((GREEKS) ? 2 : FV_LBR_WAVES_PER_EU)
 #define FV_WAVES_HALLEY(GREEKS) ((GREEKS) ? 2 : FV_HALLEY_WAVES_PER_EU)
-// The ragged kernel keeps its CSR windows live across the solve; held to the
-// flat kernel's 4 waves per SIMD (<= 128 VGPRs).
+// The ragged kernel: at least 4 waves per SIMD (<= 128 VGPRs); its LBR form
+// takes 54 VGPRs and its Halley form 75.
 #ifndef FV_CHAINS_WAVES_PER_EU
 #define FV_CHAINS_WAVES_PER_EU 4
 #endif
