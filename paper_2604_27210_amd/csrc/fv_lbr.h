@@ -221,7 +221,7 @@ __host__ __device__ __attribute__((always_inline)) inline double lbr_initial_gue
   } else {
     xl = nc.b; xr = no.b; yl = sc; yr = so; dl = ibc; dr = ibo;
   }
-  const double cl = 2.0 * kPi * ax / (3.0 * kSqrt3);
+  const double cl = ax * (2.0 * kPi / (3.0 * kSqrt3));  // 2 pi |x| / (3 sqrt3)
   if (wing) {
     // R1 / R4 share one Phi/phi evaluation at the transformed boundary point
     // (lower map: z = -|x|/(sqrt3 s_l); upper map: z = -s_u/2).  With
@@ -435,20 +435,24 @@ __host__ __device__ __attribute__((always_inline)) inline HalleyState halley_sol
   const bool logres = ln_beta < kLnBetaLogResidual;
   int region;
   double s = lbr_initial_guess(x, beta, bmax, ln_beta, &region, nullptr);
+  // the guess-precision first step only from the guess (whose |h| is
+  // bounded); from the fallback start every step is at full precision
+  int lo_steps = 1;
   if (!(s > 0.0 && s < 1e300)) {
     const double s_bs = kSqrt2Pi * beta;
     s = x < 0.0 ? fmax(s_bs, -x * rsqrt(-2.0 * ln_beta)) : s_bs;
+    lo_steps = 0;
   }
   double ds = 0.0, res = 0.0;
   bool stop = false;
   int k = 0;
   while (k < steps) {
-    const double sn = k == 0 ? halley_step_t<1>(x, beta, bmax, ln_beta, logres, s, st, res)
-                             : halley_step_t<0>(x, beta, bmax, ln_beta, logres, s, st, res);
+    const double sn = k < lo_steps ? halley_step_t<1>(x, beta, bmax, ln_beta, logres, s, st, res)
+                                     : halley_step_t<0>(x, beta, bmax, ln_beta, logres, s, st, res);
     ds = sn - s;
     s = sn;
     ++k;
-    stop = k >= 2 && fabs(ds) <= kHalleyStepTol * s;
+    stop = k > lo_steps && fabs(ds) <= kHalleyStepTol * s;
     if (stop) break;
   }
   st.s = s;

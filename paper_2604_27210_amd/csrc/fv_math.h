@@ -409,8 +409,21 @@ __host__ __device__ inline NBlack normalised_black_t(double x, double s, double 
   constexpr const double* kC = P == 0 ? coef::kErfcx : (P == 1 ? coef::kErfcxLo : coef::kErfcxG);
   constexpr double kB = P == 0 ? coef::kErfcxB : (P == 1 ? coef::kErfcxLoB : coef::kErfcxGB);
   constexpr double kShift = kB - 2.0 * coef::kErfcxZ0;
-  const double R1 = LO ? rcp_lo(z1 + kB) : rcp(z1 + kB);
-  const double R2 = LO ? rcp_lo(q2 + kB) : rcp(q2 + kB);
+  // R1 = 1/(z1 + B), R2 = 1/(q2 + B).  At guess precision (P >= 1: the
+  // initial guess and the first step, where |h| stays below about 70, so
+  // the product below neither overflows nor loses range) both come from
+  // one reciprocal of the product; full precision keeps two, which hold for
+  // any s above 2^-1000.
+  const double a1 = z1 + kB, a2 = q2 + kB;
+  double R1, R2;
+  if (LO) {
+    const double R12 = rcp_lo(a1 * a2);
+    R1 = R12 * a2;
+    R2 = R12 * a1;
+  } else {
+    R1 = rcp(a1);
+    R2 = rcp(a2);
+  }
   const double y1 = (z1 - kShift) * R1, y2 = (q2 - kShift) * R2;
   // B = p(y2), D = (p(y1) - p(y2))/(y1 - y2) by two Horner recurrences
   double B = kC[kDeg], D = 0.0;

@@ -101,29 +101,29 @@ __host__ __device__ inline double log_moneyness(double F, double K) {
 
 __host__ __device__ inline Reduced reduce_quote(int model, double price, double fs, double K,
                                                 double T, double r, double q, int theta) {
+  // One exit: every lane computes every field and the status is decided at
+  // the end, in the order of the checks below (invalid input first).  The
+  // fields of a quote whose status is not OK are meaningless and no caller
+  // reads them; early returns would instead make every path set defaults.
   Reduced o;
-  o.F = 0.0; o.D = 0.0; o.isqrtT = 0.0; o.x = 0.0; o.beta = 0.0; o.bmax = 0.0; o.lnb = 0.0;
   // S/F and K must be normal numbers (the refined hardware reciprocals
   // below need normal operands); so must the forward
   const bool ok_in = finite_d(price) && finite_d(fs) && finite_d(K) && finite_d(T) &&
                      finite_d(r) && finite_d(q) && fs >= kDblMin && K >= kDblMin && T > 0.0 &&
                      (theta == 1 || theta == -1);
-  if (!ok_in) { o.status = kQInvalid; return o; }
   const double F = forward_of(model, fs, T, r, q);
-  if (!(F >= kDblMin && finite_d(F))) { o.status = kQInvalid; return o; }
+  const bool ok_f = F >= kDblMin && finite_d(F);
   const double D = fexp_prod(-r, T);
   const double Pu = price * fexp_prod(r, T);
-  const double I = theta > 0 ? fmax(F - K, 0.0) : fmax(K - F, 0.0);
+  const double dth = (double)theta;
+  const double I = fmax(dth * (F - K), 0.0);  // intrinsic value (the sign flip is exact)
   const double M = theta > 0 ? F : K;
   o.F = F;
   o.D = D;
   o.isqrtT = rsqrt_pos(T);
-  if (Pu < I) { o.status = kQBelowIntrinsic; return o; }
-  if (Pu == I) { o.status = kQAtIntrinsic; return o; }
-  if (Pu >= M) { o.status = kQAboveMax; return o; }
-  const int th = (I > 0.0) ? -theta : theta;  // in the money: parity to OTM
-  const double lx = log_moneyness(F, K);
-  o.x = th > 0 ? lx : -lx;
+  // in the money: parity to out of the money
+  const double th = I > 0.0 ? -dth : dth;
+  o.x = th * log_moneyness(F, K);
   // 1/sqrt(F K) as two factors: F K itself leaves the binary64 range once F
   // and K are beyond about 1e+-154, while the normalised quantities do not
   // (and scaling price, F and K by an even power of two scales both factors
@@ -131,8 +131,6 @@ __host__ __device__ inline Reduced reduce_quote(int model, double price, double 
   const double isq = rsqrt(F) * rsqrt(K);
   o.beta = (Pu - I) * isq;
   o.bmax = fmin(F, K) * isq;
-  // the normalised price can round onto its bound even when Pu < M
-  o.status = (o.beta < o.bmax) ? kQOk : kQAboveMax;
   if (o.beta < 0x1p-1000 && I == 0.0) {
     // out of the money with a price too small for beta to keep full precision
     // in binary64: ln beta = ln P + r T - ln(F K)/2 from the price itself
@@ -140,6 +138,13 @@ __host__ __device__ inline Reduced reduce_quote(int model, double price, double 
   } else {
     o.lnb = flog(o.beta);
   }
+  // the normalised price can round onto its bound even when Pu < M
+  uint8_t st = o.beta < o.bmax ? kQOk : kQAboveMax;
+  if (Pu >= M) st = kQAboveMax;
+  if (Pu == I) st = kQAtIntrinsic;
+  if (Pu < I) st = kQBelowIntrinsic;
+  if (!(ok_in && ok_f)) st = kQInvalid;
+  o.status = st;
   return o;
 }
 
