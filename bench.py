@@ -38,10 +38,10 @@ if ROOT not in sys.path:
 # The traffic figure is reported only while the kernel sources still hash to
 # ``source_sha256``; the FLOP figure is the algorithmic count of that source.
 LBR_PROFILE = {
-    "source_sha256": "c82db2f86f3b066f35e71ddb7d18be7aeed0dee49d9cce275571fff6c302979a",
-    "flop_per_quote": 1120.2,
-    "valu_per_quote": 1108.8,
-    "fetch_bytes_per_quote": 50.037,
+    "source_sha256": "9abab64c824560ff8ff775944ceb34dd00bbf78f23940e899df52299778c6c36",
+    "flop_per_quote": 1092.2,
+    "valu_per_quote": 1049.1,
+    "fetch_bytes_per_quote": 50.036,
     "write_bytes_per_quote": 9.000,
 }
 FP64_VECTOR_PEAK_TFLOPS = 78.6

@@ -437,22 +437,26 @@ __host__ __device__ __attribute__((always_inline)) inline HalleyState halley_sol
   double s = lbr_initial_guess(x, beta, bmax, ln_beta, &region, nullptr);
   // the guess-precision first step only from the guess (whose |h| is
   // bounded); from the fallback start every step is at full precision
-  int lo_steps = 1;
-  if (!(s > 0.0 && s < 1e300)) {
+  const bool from_guess = s > 0.0 && s < 1e300;
+  if (!from_guess) {
     const double s_bs = kSqrt2Pi * beta;
     s = x < 0.0 ? fmax(s_bs, -x * rsqrt(-2.0 * ln_beta)) : s_bs;
-    lo_steps = 0;
   }
   double ds = 0.0, res = 0.0;
   bool stop = false;
   int k = 0;
+  if (from_guess && steps > 0) {
+    const double sn = halley_step_t<1>(x, beta, bmax, ln_beta, logres, s, st, res);
+    ds = sn - s;
+    s = sn;
+    k = 1;
+  }
   while (k < steps) {
-    const double sn = k < lo_steps ? halley_step_t<1>(x, beta, bmax, ln_beta, logres, s, st, res)
-                                     : halley_step_t<0>(x, beta, bmax, ln_beta, logres, s, st, res);
+    const double sn = halley_step_t<0>(x, beta, bmax, ln_beta, logres, s, st, res);
     ds = sn - s;
     s = sn;
     ++k;
-    stop = k > lo_steps && fabs(ds) <= kHalleyStepTol * s;
+    stop = fabs(ds) <= kHalleyStepTol * s;
     if (stop) break;
   }
   st.s = s;
