@@ -316,7 +316,9 @@ int fv_get_halley_steps(void);
  * overrides the launch shape of one kernel family (FV_KERNEL_*); block must
  * be a multiple of 64 in [64, 512] and quotes_per_thread in [1, 16], and for
  * the Halley families the workgroup's queue of unconverged quotes (24 bytes
- * per quote, 16 for binary32) must fit in 64 KiB of LDS
+ * per quote, 16 for binary32; the ragged-chain kernel, which takes two
+ * 64-quote slices per wave and ignores quotes_per_thread, 64 bytes per
+ * thread) must fit in 64 KiB of LDS
  * (FV_E_INVALID_ARG otherwise; the shape in force is kept).
  * fv_get_launch reads the configured shape.  The shape applies as set to
  * batches large enough to fill the device; a batch that would give fewer
