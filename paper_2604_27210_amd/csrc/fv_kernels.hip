@@ -98,7 +98,7 @@ constexpr int kMaxBlock = 512;
 #define FV_WAVES_LBR(GREEKS) ((GREEKS) ? 2 : FV_LBR_WAVES_PER_EU)
 #define FV_WAVES_HALLEY(GREEKS) ((GREEKS) ? 2 : FV_HALLEY_WAVES_PER_EU)
 // The ragged kernel: at least 4 waves per SIMD (<= 128 VGPRs); its LBR form
-// takes 54 VGPRs and its Halley form 75.
+// takes 62 VGPRs and its Halley form 83.
 #ifndef FV_CHAINS_WAVES_PER_EU
 #define FV_CHAINS_WAVES_PER_EU 4
 #endif
