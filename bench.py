@@ -38,7 +38,7 @@ if ROOT not in sys.path:
 # The traffic figure is reported only while the kernel sources still hash to
 # ``source_sha256``; the FLOP figure is the algorithmic count of that source.
 LBR_PROFILE = {
-    "source_sha256": "5222cb47e8a44e6f9b88214ae7a169c9c8f37002d66af31e66ba467827052685",
+    "source_sha256": "d56dfe3928839ac23a24d1a7670bd36fae386c46fb364b5d604031a11bfe7078",
     "flop_per_quote": 1092.2,
     "valu_per_quote": 1049.1,
     "fetch_bytes_per_quote": 50.036,
