@@ -38,7 +38,7 @@ if ROOT not in sys.path:
 # The traffic figure is reported only while the kernel sources still hash to
 # ``source_sha256``; the FLOP figure is the algorithmic count of that source.
 LBR_PROFILE = {
-    "source_sha256": "d56dfe3928839ac23a24d1a7670bd36fae386c46fb364b5d604031a11bfe7078",
+    "source_sha256": "73229bffb128651aa572b16bca53cb34c397e675225862919c8ae30cf4a7d2b9",
     "flop_per_quote": 1092.2,
     "valu_per_quote": 1049.1,
     "fetch_bytes_per_quote": 50.036,
