@@ -146,3 +146,16 @@ def test_fuzz_extreme_ranges_f32(fv, model):
     n_ok, worst = check(fv, model, P, S, K, T, r, q, flag)
     print("f32 fuzz %s: solved %d of %d, max err/tol %.3g" % (model, n_ok, len(P), worst))
     assert n_ok > 0.5 * len(P)
+
+
+def test_fallback_forced_by_step_limit_f32(fv):
+    """The binary32 bisection fallback, with the Halley step limit lowered to
+    1 from the host so that most quotes go through the LDS queue: the
+    results still meet the binary32 contract, element by element."""
+    wl = W.bsm_wide(100_000, seed=2)
+    fv.set_halley_steps(1)
+    try:
+        n, worst = check(fv, "bsm", assemble_prices(wl), wl.fs, wl.K, wl.T, wl.r, wl.q, wl.flag)
+    finally:
+        fv.set_halley_steps(8)
+    assert n > 75_000 and worst <= 1.0
