@@ -30,6 +30,8 @@ if ROOT not in sys.path:
 #    VALU instruction = 1 per lane) from SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64
 #    of one launch over the workload with the quotes sorted by LBR path
 #    (``--census``), where no wave executes a branch another lane skipped;
+#  * executed_flop_per_quote: the same count on the workload as generated
+#    (divergence included);
 #  * valu_per_quote: SQ_INSTS_VALU x 64 / quotes of the same sorted launch,
 #    every vector instruction (compares, selects, conversions included);
 #  * fetch/write_bytes_per_quote: FETCH_SIZE and WRITE_SIZE of the timed
@@ -40,6 +42,7 @@ if ROOT not in sys.path:
 LBR_PROFILE = {
     "source_sha256": "73229bffb128651aa572b16bca53cb34c397e675225862919c8ae30cf4a7d2b9",
     "flop_per_quote": 1092.2,
+    "executed_flop_per_quote": 1219.3,
     "valu_per_quote": 1049.1,
     "fetch_bytes_per_quote": 50.036,
     "write_bytes_per_quote": 9.000,
@@ -754,6 +757,12 @@ def main():
         roof = {"bound": "alu", "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
                 "flop_per_quote": LBR_PROFILE["flop_per_quote"],
+                # the FP64 work the launch executes on the workload as
+                # generated (lanes a wave carries through branches they do
+                # not take included), against the same peak: context for
+                # frac, which counts the algorithmic work only
+                "executed_frac": LBR_PROFILE["executed_flop_per_quote"] * a.n / avg_kernel_s / 1e12
+                                 / FP64_VECTOR_PEAK_TFLOPS,
                 # share of the chip's VALU issue capacity at 2.4 GHz that the
                 # launch's census vector instructions fill
                 "valu_issue_frac": LBR_PROFILE["valu_per_quote"] * a.n /
