@@ -264,10 +264,13 @@ def host_fp64_lbr(wl, P, sample, reps=3):
     cmd = ["g++", "-O3", "-march=native", "-std=gnu++17", "-fopenmp", "-shared", "-fPIC",
            "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"),
            "-I" + csrc, src, "-o", so]
+    import shutil
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
+        shutil.rmtree(d, ignore_errors=True)
         return {"error": "host build failed: " + res.stderr[-300:]}
     lib = ctypes.CDLL(so)
+    shutil.rmtree(d, ignore_errors=True)  # the loaded library stays mapped
     idx = np.linspace(0, wl.n - 1, sample).astype(np.int64)
     sub = wl.take(idx)
     arrs = [np.ascontiguousarray(a, dtype=np.float64)
