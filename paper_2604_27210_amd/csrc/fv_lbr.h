@@ -237,7 +237,10 @@ __host__ __device__ __attribute__((always_inline)) inline double lbr_initial_gue
       const double zp = -z * iso;  // dz/ds
       f0 = cl * Pz * Pz * Pz;
       f1 = 3.0 * cl * Pz * Pz * pz * zp;
-      f2 = 3.0 * cl * zp * zp * Pz * pz * (2.0 * pz - Pz * z - 2.0 * Pz * iso * rcp_lo(zp));
+      // d2f/ds2 = 3 cl z'^2 Phi phi (2 phi - Phi z + 2 Phi/z); with
+      // z = -|x|/(sqrt3 s) the last term times cl is -(4 pi/3) Phi s_o, so
+      // no division is needed
+      f2 = 3.0 * zp * zp * Pz * pz * fma(cl, fma(-Pz, z, 2.0 * pz), -(4.0 * kPi / 3.0) * Pz * so);
     } else {
       f0 = Pz;
       f1 = -0.5 * pz;
@@ -257,24 +260,18 @@ __host__ __device__ __attribute__((always_inline)) inline double lbr_initial_gue
   if (!wing) return y;
   // invert the map: R1 Phi(z) = (f/cl)^{1/3}, s = -|x|/(sqrt3 z);
   //                 R4 Phi(-s/2) = f,          s = -2 z.
-  // The lower-map cubic leaves (0, 0) with slope 1, so for a beta below the
-  // normal range f = beta (1 + O(beta)): then ln p = (ln beta - ln cl)/3 is
-  // taken from ln beta, which stays finite where f and p underflow.
-  // R1: p = (f/cl)^{1/3} as exp(ln(f/cl)/3), ln(f/cl) from ln beta where
-  // the cubic's value is below the normal range; R4: p = f.  One logarithm
-  // either way.
+  // The inverse normal needs only ln p: R1 ln p = ln(f/cl)/3, R4 ln p = ln f,
+  // one logarithm either way.  The lower-map cubic leaves (0, 0) with slope
+  // 1, so for a beta below the normal range f = beta (1 + O(beta)): there
+  // ln(f/cl) is taken as ln beta - ln cl, which stays finite where f
+  // underflows.
   const double f = fmax(y, 1e-300);
   const bool deep = r1 && y < 0x1p-960;
   const double la = flog_lo(r1 ? (deep ? cl : f * rcp_lo(cl)) : fmin(f, 0.5));
-  double p, lnp;
-  if (r1) {
-    lnp = fmin((deep ? ln_beta - la : la) * (1.0 / 3.0), -0.69314718076);  // p <= 0.4999999999
-    p = deep ? 0.0 : fexp_g(lnp);
-  } else {
-    lnp = la;
-    p = fmin(f, 0.5);
-  }
-  const double zi = inv_norm_cdf_lower_ln_g(p, lnp);
+  const double lnp = r1 ? fmin((deep ? ln_beta - la : la) * (1.0 / 3.0),
+                               -0.69314718076)  // p <= 0.4999999999
+                        : la;
+  const double zi = inv_norm_cdf_lower_ln_g(lnp);
   return r1 ? -ax * (1.0 / kSqrt3) * rcp_lo(zi) : -2.0 * zi;
 }
 

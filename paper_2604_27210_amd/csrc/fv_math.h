@@ -286,22 +286,22 @@ __host__ __device__ inline double norm_cdf(double z) {
   return z < 0.0 ? tail : 1.0 - tail;
 }
 
-// Inverse standard normal CDF for p in (0, 1/2] (returns a value <= 0), as
-// (p - 1/2) P(r)/Q(r) with r = sqrt(-2 ln p): one [5/5] rational on the
-// whole range, relative error ~7e-5 (fitted, fv_coeffs.h).  Only the
-// initial guess uses it, with p's logarithm lnp (which stays finite when p
-// underflows: then p - 1/2 is -1/2).
+// Inverse standard normal CDF for p in (0, 1/2] (returns a value <= 0), from
+// ln p alone: (r - r0) P(r)/Q(r) with r = sqrt(-2 ln p) and r0 = sqrt(2 ln 2)
+// (r at p = 1/2, where the inverse has its simple zero), one [3/3] rational
+// on the whole range, relative error ~2e-6 (fitted, fv_coeffs.h).  Only the
+// initial guess uses it; ln p stays finite where p itself underflows.
 constexpr int kPhiInvGDegP = (int)(sizeof(coef::kPhiInvGP) / sizeof(double)) - 1;
 constexpr int kPhiInvGDegQ = (int)(sizeof(coef::kPhiInvGQ) / sizeof(double)) - 1;
 
-__host__ __device__ inline double inv_norm_cdf_lower_ln_g(double p, double lnp) {
+__host__ __device__ inline double inv_norm_cdf_lower_ln_g(double lnp) {
   const double r = sqrt_lo(-2.0 * lnp);
   double num = coef::kPhiInvGP[kPhiInvGDegP], den = coef::kPhiInvGQ[kPhiInvGDegQ];
 #pragma unroll
   for (int i = kPhiInvGDegP - 1; i >= 0; --i) num = fma(num, r, coef::kPhiInvGP[i]);
 #pragma unroll
   for (int i = kPhiInvGDegQ - 1; i >= 0; --i) den = fma(den, r, coef::kPhiInvGQ[i]);
-  return (p - 0.5) * fdiv_lo(num, den);
+  return (r - coef::kPhiInvGR0) * fdiv_lo(num, den);
 }
 
 // ---------------------------------------------------- normalised Black

@@ -30,12 +30,14 @@ definitions evaluated in mpmath (no coefficients are taken from any library):
    serves the binary32 solver, where binary32 rounding dominates both.
 
 2. The inverse standard normal CDF on (0, 1/2] (initial guess only), as one
-   [5/5] rational function in the tail variable r = sqrt(-2 ln p) of the
-   ratio G(r) = Phi^{-1}(p)/(p - 1/2): G -> sqrt(2 pi) at p = 1/2 and grows
-   like 2r in the tail, smooth on the whole range, so one branch covers
-   p in [1e-310, 1/2] without the central/tail split of Wichura's AS 241
-   (Appl. Stat. 37, 1988).  Fitted by iteratively re-weighted linearised
-   least squares (relative error ~7e-5, ample for a starting point that
+   [3/3] rational function in the tail variable r = sqrt(-2 ln p) of the
+   ratio G(r) = Phi^{-1}(p)/(r - r0), r0 = sqrt(2 ln 2) the value of r at
+   p = 1/2 (where Phi^{-1} has its simple zero): G is smooth and bounded
+   away from zero on the whole range and tends to -1 in the tail, so one
+   branch covers p in [1e-310, 1/2] without the central/tail split of
+   Wichura's AS 241 (Appl. Stat. 37, 1988), and the caller needs only
+   ln p, never p itself.  Fitted by iteratively re-weighted linearised
+   least squares (relative error ~2e-6, ample for a starting point that
    lands a few percent from the root).
 """
 from __future__ import annotations
@@ -53,7 +55,7 @@ ERFCX_F32_B = mp.mpf("3.5")
 ERFCX_F32_DEG = 13
 ERFCX_G_B = mp.mpf("3.0")
 ERFCX_G_DEG = 7
-PHI_INV_G_DEG = (5, 5)
+PHI_INV_G_DEG = (3, 3)
 P_MIN = mp.mpf("1e-310")
 
 
@@ -142,24 +144,26 @@ def fit_rational(ts, fs, m, n, iters=4):
 
 def fit_phi_inv(N=80, deg=PHI_INV_G_DEG):
     half = mp.mpf("0.5")
-    ra = mp.sqrt(-2 * mp.log(half))
+    ra = mp.sqrt(-2 * mp.log(half))  # r0: r at p = 1/2
     rb = mp.sqrt(-2 * mp.log(P_MIN))
     rs = [(ra + rb) / 2 + (rb - ra) / 2 * mp.cos(mp.pi * (k + half) / N) for k in range(N)]
     fs = []
     for r in rs:
         p = mp.exp(-r * r / 2)
-        fs.append(ndtri(p) / (p - half))
+        fs.append(ndtri(p) / (r - ra))
     P, Q, _ = fit_rational(rs, fs, *deg, iters=6)
-    # relative error of Phi^{-1} itself on a dense grid (coefficients rounded)
+    # relative error of Phi^{-1} itself on a dense grid (coefficients and r0
+    # rounded to binary64)
     Pd = [mp.mpf(float(v)) for v in P]
     Qd = [mp.mpf(float(v)) for v in Q]
+    r0d = mp.mpf(float(ra))
     err = mp.mpf(0)
     for k in range(1, 400):
         r = ra + (rb - ra) * mp.mpf(k) / 400
         p = mp.exp(-r * r / 2)
         g = mp.polyval(Pd[::-1], r) / mp.polyval(Qd[::-1], r)
-        err = max(err, abs(g * (p - half) / ndtri(p) - 1))
-    return P, Q, err
+        err = max(err, abs(g * (r - r0d) / ndtri(p) - 1))
+    return P, Q, ra, err
 
 
 def _arr(name, vals):
@@ -177,7 +181,7 @@ def main():
     f32_err, f32_deriv = check_erfcx(e32, ERFCX_F32_B)
     eg = fit_erfcx(ERFCX_G_B, ERFCX_G_DEG)
     g_err, g_deriv = check_erfcx(eg, ERFCX_G_B)
-    gP, gQ, gerr = fit_phi_inv()
+    gP, gQ, gr0, gerr = fit_phi_inv()
     n3 = lambda v: mp.nstr(v, 3)
     out = [
         "// Generated by gen_coeffs.py -- do not edit by hand.\n",
@@ -189,8 +193,8 @@ def main():
         % (n3(f32_err), n3(f32_deriv)),
         "// initial-guess erfcx (same form, B = kErfcxGB): max rel err %s, derivative %s\n"
         % (n3(g_err), n3(g_deriv)),
-        "// Inverse normal CDF on (0, 1/2]: Phi^{-1}(p) = (p - 1/2) P(r)/Q(r),\n",
-        "// r = sqrt(-2 ln p), [5/5]; max rel err %s\n" % n3(gerr),
+        "// Inverse normal CDF on (0, 1/2]: Phi^{-1}(p) = (r - r0) P(r)/Q(r),\n",
+        "// r = sqrt(-2 ln p), r0 = sqrt(2 ln 2), [3/3]; max rel err %s\n" % n3(gerr),
         "#pragma once\n\nnamespace fv {\nnamespace coef {\n\n",
         "constexpr double kErfcxZ0 = %s;\n" % mp.nstr(ERFCX_Z0, 20),
         "constexpr double kErfcxB = %s;\n" % mp.nstr(ERFCX_B, 20),
@@ -202,6 +206,7 @@ def main():
         "\nconstexpr double kErfcxGB = %s;\n" % mp.nstr(ERFCX_G_B, 20),
         _arr("kErfcxG", eg),
         "\n",
+        "constexpr double kPhiInvGR0 = %s;\n" % mp.nstr(gr0, 20),
         _arr("kPhiInvGP", gP),
         _arr("kPhiInvGQ", gQ),
         "\n}  // namespace coef\n}  // namespace fv\n",
