@@ -40,11 +40,11 @@ if ROOT not in sys.path:
 # The traffic figure is reported only while the kernel sources still hash to
 # ``source_sha256``; the FLOP figure is the algorithmic count of that source.
 LBR_PROFILE = {
-    "source_sha256": "73229bffb128651aa572b16bca53cb34c397e675225862919c8ae30cf4a7d2b9",
-    "flop_per_quote": 1092.2,
-    "executed_flop_per_quote": 1219.3,
-    "valu_per_quote": 1049.1,
-    "fetch_bytes_per_quote": 50.036,
+    "source_sha256": "07506ec4e603578bce41630df4e9a1a4b067c5a208677fa6be7c9fa8ba395d60",
+    "flop_per_quote": 1082.5,
+    "executed_flop_per_quote": 1205.6,
+    "valu_per_quote": 1038.6,
+    "fetch_bytes_per_quote": 50.033,
     "write_bytes_per_quote": 9.000,
 }
 FP64_VECTOR_PEAK_TFLOPS = 78.6
